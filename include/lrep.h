@@ -1,0 +1,210 @@
+/*
+ * lrep.h -- C ABI of the MI355X (gfx950) BOSP eigensolver for the linear
+ * response eigenvalue problem (LREP).
+ *
+ * Problem (paper Section 1, change of variables u = y + x, v = y - x):
+ *
+ *     [[A, B], [-B, -A]] [u; v] = lambda [u; v]   <=>   H [y; x] = lambda [y; x],
+ *     H = [[0, K], [M, 0]],  K = A - B,  M = A + B,
+ *
+ * i.e. K x = lambda y and M y = lambda x, with K symmetric positive
+ * semi-definite and M symmetric positive definite (or the reverse, see
+ * LREP_NULL_ON_M).  lrep_solve returns the nev smallest positive eigenvalues
+ * in ascending order with X^T Y = I (Algorithm "BOSP algorithm", Sections
+ * 3.2-3.3 of the paper).
+ *
+ * Conventions for every entry point
+ *   - matrices are column-major IEEE FP64 with an explicit leading dimension
+ *     (ld >= number of rows);
+ *   - pointers are host pointers unless a flag or option says "device"
+ *     (a device pointer is a HIP device allocation on the context's device);
+ *   - every function returns 0 (LREP_OK) or a negative LREP_E* code and never
+ *     aborts; lrep_strerror(code) gives a static message and
+ *     lrep_last_error(ctx) the detail of the last failure on a context;
+ *   - the library owns every workspace it allocates; the caller owns every
+ *     buffer it passes.
+ */
+#ifndef LREP_H
+#define LREP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define LREP_OK           0
+#define LREP_EINVAL      -1   /* bad argument: sizes, null pointer, nev > n - r, ...   */
+#define LREP_ENOMEM      -2   /* HBM budget of the context or hipMalloc exhausted       */
+#define LREP_ENOTCONV    -3   /* maxit reached; converged prefix written, count in stats */
+#define LREP_EBREAKDOWN  -4   /* MGS-Biorth dropped so many columns that the subspace
+                                 cannot hold the requested Ritz block                   */
+#define LREP_ENOTSPD     -5   /* Cholesky of a projected matrix failed (operator not
+                                 SPD on the subspace)                                   */
+#define LREP_ENUMERIC    -6   /* NaN or Inf met (operator or iteration)                 */
+#define LREP_EDEVICE     -7   /* HIP runtime error, detail in lrep_last_error           */
+#define LREP_EAGAIN      -8   /* lrep_poll: request still pending                        */
+#define LREP_ECANCELED   -9   /* lrep_poll: request was cancelled                        */
+
+/* ---------------------------------------------------------------- flags */
+#define LREP_DEVICE_PTR  0x1u /* operator arrays are device pointers                   */
+#define LREP_BORROW      0x2u /* with LREP_DEVICE_PTR: use the caller's device arrays in
+                                 place (caller keeps them alive and unchanged until
+                                 lrep_destroy_op); otherwise they are copied            */
+#define LREP_INPUT_AB    0x4u /* dense: the two matrices are A and B; the library forms
+                                 K = A - B and M = A + B (paper Section 1)              */
+#define LREP_NULL_ON_M   0x8u /* the semi-definite operator is M, not K: the solver
+                                 exchanges the roles of K and M (exact:
+                                 K x = l y, M y = l x <=> M y = l x, K x = l y with
+                                 x, y exchanged) and exchanges X, Y back on output    */
+
+typedef struct lrep_ctx_s* lrep_ctx_t;
+typedef struct lrep_op_s*  lrep_op_t;
+typedef uint64_t           lrep_ticket_t;
+
+/* Solver options.  Zero-initialise and set what you need; every zero field
+ * takes the documented default. */
+typedef struct lrep_solve_opts {
+    int64_t window;        /* w = n_b, width of the P/Q and W/Z blocks (default: block) */
+    int64_t maxit;         /* outer iterations (default 1000)                          */
+    int32_t ngs;           /* block Gauss-Seidel sweeps in Step 6 (default 1)           */
+    int32_t cg_maxit;      /* CG iterations per solve (default 20)                      */
+    double  cg_tol;        /* CG relative residual tolerance (default 1e-2)             */
+    uint64_t seed;         /* seed of the library's own starting block (Philox4x32-10,
+                              Box-Muller) when init_U is NULL                           */
+    const double* init_U;  /* optional starting block, n x (block + 2 window), ld_init;
+                              used for both U and V (the paper's Step 1)                */
+    int64_t ld_init;
+    int32_t init_on_device;   /* init_U is a device pointer                             */
+    int32_t result_on_device; /* lambda, X, Y are device pointers                       */
+    int32_t precision;        /* 0: FP64 everywhere (default)                          */
+    int32_t reserved0;
+    double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this
+                              (default 1e-12)                                          */
+} lrep_solve_opts_t;
+
+/* Per-solve statistics (all optional to read). */
+typedef struct lrep_stats {
+    int64_t iterations;        /* outer iterations run                                 */
+    int64_t n_converged;       /* eigenpairs written (== nev on LREP_OK)               */
+    int64_t applies_K;         /* column mat-vecs with K                               */
+    int64_t applies_M;         /* column mat-vecs with M                               */
+    int64_t mgs_drops;         /* columns dropped by MGS-Biorth breakdown handling      */
+    int64_t locks;             /* moving-mechanism lock events                          */
+    int64_t rebiorth;          /* biorthogonality restorations                          */
+    double  max_eps;           /* max Step-4 residual of the returned pairs            */
+    double  time_ms;           /* wall time of the solve                               */
+    /* per-phase GPU time (ms) in the paper's five buckets: initialise U,V /
+       small-scale problem (incl. projection and pull-back) / convergence check /
+       P,Q / W,Z (incl. CG and MGS-Biorth)                                         */
+    double  phase_ms[5];
+} lrep_stats_t;
+
+/* Request for the serving interface (lrep_submit). */
+typedef struct lrep_request {
+    int64_t nev;
+    int64_t block;
+    double  tol;
+    lrep_solve_opts_t opts;    /* as for lrep_solve; result_on_device applies        */
+    double* lambda;            /* nev                                                 */
+    double* X;                 /* n x nev, ld = ldxy                                  */
+    double* Y;
+    int64_t ldxy;
+} lrep_request_t;
+
+/* ------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold for operators and workspaces (0 = no
+ * cap beyond the device).  `hip_stream` is a hipStream_t to run on, or NULL
+ * for a stream the context creates (default priority).
+ * Errors: LREP_EINVAL (bad device), LREP_EDEVICE. */
+int lrep_init(lrep_ctx_t* ctx, int device, size_t hbm_budget_bytes, void* hip_stream);
+
+/* Destroy the context: cancels pending requests, waits for the running one,
+ * frees every workspace.  Operators must be destroyed first (else they are
+ * destroyed here). */
+int lrep_finalize(lrep_ctx_t ctx);
+
+/* ----------------------------------------------------------- operators */
+
+/* Dense operator (paper equation for H).  K and M are n x n symmetric,
+ * column-major with leading dimension ld (with LREP_INPUT_AB they are A and
+ * B).  Only the lower triangle is read when symmetrising is not needed; both
+ * triangles are used by the apply.  Host arrays are copied to HBM; device
+ * arrays are copied, or borrowed with LREP_BORROW.
+ * Errors: LREP_EINVAL (n < 1, ld < n, null pointer), LREP_ENOMEM, LREP_EDEVICE. */
+int lrep_create_dense(lrep_ctx_t ctx, int64_t n, const double* K, const double* M,
+                      int64_t ld, uint32_t flags, lrep_op_t* op);
+
+/* Diagonal-plus-low-rank (Casida-type) operator, matrix-free:
+ *     K = diag(delta),  M = diag(delta) + 2 L L^T,
+ * delta: n values (> 0), L: n x rank column-major with leading dimension ldl.
+ * Storage on the device is n + n*rank doubles.
+ * Errors: LREP_EINVAL, LREP_ENOMEM, LREP_EDEVICE. */
+int lrep_create_lowrank(lrep_ctx_t ctx, int64_t n, int64_t rank, const double* delta,
+                        const double* L, int64_t ldl, uint32_t flags, lrep_op_t* op);
+
+/* Declare the generalized null space (Lemma 2.3, Remark on computing V0):
+ * X0 (n x r, ld) spans N(K) (or N(M) with LREP_NULL_ON_M).  The library
+ * solves M Y0~ = X0~ by CG on the device, factors X0~^T Y0~ = C^T C and keeps
+ * X0 = X0~ C^-1, Y0 = Y0~ C^-1 (equation for the V0 basis) so that every
+ * later iterate is biorthogonal to V0.  r = 0 clears it.
+ * Errors: LREP_EINVAL, LREP_ENOTSPD (X0~^T Y0~ not SPD), LREP_ENOMEM. */
+int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, int32_t on_device);
+
+/* Free an operator's device memory (borrowed arrays are not freed). */
+int lrep_destroy_op(lrep_op_t op);
+
+/* --------------------------------------------------------------- solve */
+
+/* Blocking solve on the context's stream (Algorithm "BOSP algorithm").
+ *   n      must equal the operator's dimension;
+ *   nev    number of eigenpairs, 1 <= nev <= n - r;
+ *   block  width b of the Ritz block X (b = s * n_b under the moving
+ *          mechanism); the subspace has d = b + 2w columns, w = opts->window;
+ *          requires d <= n - r and d <= 128 (the small problem runs in one
+ *          workgroup on the device);
+ *   tol    stopping tolerance on ||H z - l z|| / ((1 + l) ||z||) (Section 4);
+ *   lambda (nev), X, Y (n x nev, ld = ldxy) outputs, host or device per
+ *          opts->result_on_device; X^T Y = I, K X = Y diag(lambda),
+ *          M Y = X diag(lambda); each x is sign-normalised so that its
+ *          entry of largest magnitude is positive.
+ * Errors: LREP_EINVAL, LREP_ENOMEM, LREP_ENOTCONV (maxit reached: the
+ * converged prefix is written, stats->n_converged says how many),
+ * LREP_EBREAKDOWN, LREP_ENOTSPD, LREP_ENUMERIC, LREP_EDEVICE. */
+int lrep_solve(lrep_op_t op, int64_t n, int64_t nev, int64_t block, double tol,
+               const lrep_solve_opts_t* opts, double* lambda, double* X, double* Y,
+               int64_t ldxy, lrep_stats_t* stats);
+
+/* ------------------------------------------------------------- serving */
+
+/* Queue a solve on `op` (thread-safe).  The request struct is copied; its
+ * output buffers must stay valid until lrep_poll reports completion.
+ * Requests are admitted in arrival order as the context's HBM budget allows
+ * (a request whose workspace alone exceeds the budget fails with
+ * LREP_ENOMEM at poll time) and run concurrently with other admitted
+ * requests; results are identical to lrep_solve with the same arguments.
+ * Errors: LREP_EINVAL (bad request), LREP_ENOMEM (host allocation). */
+int lrep_submit(lrep_ctx_t ctx, lrep_op_t op, const lrep_request_t* req, lrep_ticket_t* ticket);
+
+/* Completion status of a ticket (thread-safe, non-blocking): LREP_EAGAIN
+ * while pending or running, otherwise the solve's own return code (once
+ * reported, the ticket is released).  stats_out may be NULL. */
+int lrep_poll(lrep_ctx_t ctx, lrep_ticket_t ticket, lrep_stats_t* stats_out);
+
+/* Cancel a pending ticket (a running one finishes).  LREP_EINVAL for an
+ * unknown ticket. */
+int lrep_cancel(lrep_ctx_t ctx, lrep_ticket_t ticket);
+
+/* ---------------------------------------------------------------- misc */
+const char* lrep_strerror(int code);
+const char* lrep_last_error(lrep_ctx_t ctx);
+int lrep_version(void);   /* 100 * major + minor */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LREP_H */

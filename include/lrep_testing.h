@@ -1,0 +1,45 @@
+/*
+ * lrep_testing.h -- kernel-level entry points of the BOSP library, exported
+ * for the library's own unit tests.  Each runs one internal kernel family on
+ * caller-owned device buffers, synchronously on the context's stream.  All
+ * matrices are column-major FP64 device arrays; return 0 or an LREP_E* code.
+ */
+#ifndef LREP_TESTING_H
+#define LREP_TESTING_H
+#include "lrep.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C (m x q, ldc) = alpha * A (m x p, lda) * B (p x q, ldb) + beta * C,
+ * the FP64 MFMA product used by the dense apply and the pull-back.
+ * ksplit > 0 forces the split of the p dimension (deterministic second
+ * stage), 0 lets the library choose. */
+int lrep_test_gemm_nn(lrep_ctx_t ctx, int m, int q, int p, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, double alpha, double beta, int ksplit);
+
+/* C (p x q, ldc) = A^T B, A n x p (lda), B n x q (ldb): the tall-skinny Gram
+ * product; symmetrize != 0 returns (C + C^T)/2 (p == q). */
+int lrep_test_gemm_tn(lrep_ctx_t ctx, int n, int p, int q, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, int symmetrize);
+
+/* Small structured LREP (Step 3): Kh, Mh d x d (ld ldh), d <= 128.
+ * Outputs lam (d, ascending), Xh, Yh (d x d, ld 128).  Returns
+ * LREP_ENOTSPD when a Cholesky factorisation fails. */
+int lrep_test_small_lrep(lrep_ctx_t ctx, int d, const double* Kh, const double* Mh, int64_t ldh, double* lam,
+                         double* Xh, double* Yh);
+
+/* Block MGS-Biorth (two coefficient passes) of (X, Y), n x m, ld n, m <= 128,
+ * in place; *kept receives the number of columns kept (compacted to the
+ * front). */
+int lrep_test_block_mgs(lrep_ctx_t ctx, int n, int m, double* X, double* Y, int* kept);
+
+/* Y = A X for an operator (which = 0: K, 1: M, after the role exchange of
+ * LREP_NULL_ON_M), X n x cols (ld n), Y n x cols (ld n). */
+int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* Y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,347 @@
+// C ABI of the library (declared in include/lrep.h): contexts, operators,
+// blocking solves and the request queue of the serving interface.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "internal.hpp"
+
+using namespace lrep;
+
+struct lrep_ctx_s : public Ctx {};
+struct lrep_op_s : public Op {};
+
+namespace lrep {
+
+DevBuf::~DevBuf() { release(); }
+
+int DevBuf::alloc(Ctx* c, size_t nbytes) {
+    release();
+    ctx = c;
+    if (nbytes == 0) nbytes = 8;
+    if (c->budget) {
+        size_t cur = c->used.load();
+        do {
+            if (cur + nbytes > c->budget) return LREP_ENOMEM;
+        } while (!c->used.compare_exchange_weak(cur, cur + nbytes));
+    } else {
+        c->used += nbytes;
+    }
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, nbytes);
+    if (e != hipSuccess) {
+        c->used -= nbytes;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? LREP_ENOMEM : LREP_EDEVICE;
+    }
+    p = static_cast<double*>(q);
+    bytes = nbytes;
+    return LREP_OK;
+}
+
+void DevBuf::release() {
+    if (p) {
+        (void)hipFree(p);
+        ctx->used -= bytes;
+    }
+    p = nullptr;
+    bytes = 0;
+}
+
+}  // namespace lrep
+
+namespace {
+
+int set_device(Ctx* c) {
+    return hipSetDevice(c->device) == hipSuccess ? LREP_OK : LREP_EDEVICE;
+}
+
+void worker_main(Ctx* c) {
+    (void)hipSetDevice(c->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    std::unique_lock<std::mutex> lk(c->q_mu);
+    for (;;) {
+        c->q_cv.wait(lk, [&] { return c->stopping || !c->queue.empty(); });
+        if (c->stopping && c->queue.empty()) break;
+        const uint64_t id = c->queue.front();
+        c->queue.pop_front();
+        auto it = c->tickets.find(id);
+        if (it == c->tickets.end() || it->second.state != 0) continue;
+        it->second.state = 1;
+        Ctx::Ticket t = it->second;
+        lk.unlock();
+        lrep_stats_t stats{};
+        int rc;
+        for (;;) {
+            rc = solve(t.op, st, t.req.nev, t.req.block, t.req.tol, &t.req.opts, t.req.lambda, t.req.X, t.req.Y,
+                       t.req.ldxy, &stats);
+            if (rc != LREP_ENOMEM || !c->budget) break;
+            // HBM budget exhausted by other running requests: wait for one to finish
+            std::unique_lock<std::mutex> l2(c->q_mu);
+            bool others = false;
+            for (auto& kv : c->tickets)
+                if (kv.first != id && kv.second.state == 1) others = true;
+            if (!others) break;
+            c->q_cv.wait_for(l2, std::chrono::milliseconds(20));
+        }
+        lk.lock();
+        auto it2 = c->tickets.find(id);
+        if (it2 != c->tickets.end()) {
+            it2->second.state = 2;
+            it2->second.rc = rc;
+            it2->second.stats = stats;
+        }
+        c->q_cv.notify_all();
+    }
+    lk.unlock();
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lrep_version(void) { return 100; }
+
+const char* lrep_strerror(int code) {
+    switch (code) {
+        case LREP_OK: return "success";
+        case LREP_EINVAL: return "invalid argument";
+        case LREP_ENOMEM: return "out of device memory or HBM budget";
+        case LREP_ENOTCONV: return "not converged within maxit";
+        case LREP_EBREAKDOWN: return "biorthogonalisation breakdown";
+        case LREP_ENOTSPD: return "operator not positive definite on the subspace";
+        case LREP_ENUMERIC: return "non-finite value";
+        case LREP_EDEVICE: return "HIP runtime error";
+        case LREP_EAGAIN: return "request pending";
+        case LREP_ECANCELED: return "request cancelled";
+        default: return "unknown error";
+    }
+}
+
+const char* lrep_last_error(lrep_ctx_t ctx) {
+    if (!ctx) return "";
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    return ctx->last_error.c_str();
+}
+
+int lrep_init(lrep_ctx_t* out, int device, size_t hbm_budget_bytes, void* hip_stream) {
+    if (!out) return LREP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LREP_EINVAL;
+    auto* c = new lrep_ctx_s();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (set_device(c) != LREP_OK) {
+        delete c;
+        return LREP_EDEVICE;
+    }
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return LREP_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return LREP_OK;
+}
+
+int lrep_finalize(lrep_ctx_t c) {
+    if (!c) return LREP_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(c->q_mu);
+        c->stopping = true;
+        for (auto& kv : c->tickets)
+            if (kv.second.state == 0) kv.second.state = 3;
+        c->queue.clear();
+    }
+    c->q_cv.notify_all();
+    for (auto& t : c->workers) t.join();
+    (void)hipSetDevice(c->device);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LREP_OK;
+}
+
+int lrep_create_dense(lrep_ctx_t c, int64_t n, const double* K, const double* M, int64_t ld, uint32_t flags,
+                      lrep_op_t* out) {
+    if (!c || !out || !K || !M || n < 1 || ld < n || n > (int64_t)INT32_MAX) return LREP_EINVAL;
+    *out = nullptr;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    auto* op = new lrep_op_s();
+    op->ctx = c;
+    op->n = n;
+    op->kind = 0;
+    op->flags = flags;
+    const bool dev = flags & LREP_DEVICE_PTR;
+    const bool borrow = dev && (flags & LREP_BORROW) && !(flags & LREP_INPUT_AB);
+    if (borrow) {
+        op->K = const_cast<double*>(K);
+        op->M = const_cast<double*>(M);
+        op->ld = ld;
+    } else {
+        const size_t bytes = (size_t)n * n * sizeof(double);
+        int rc = op->Kbuf.alloc(c, bytes);
+        if (rc == LREP_OK) rc = op->Mbuf.alloc(c, bytes);
+        if (rc != LREP_OK) {
+            delete op;
+            return rc;
+        }
+        op->K = op->Kbuf.p;
+        op->M = op->Mbuf.p;
+        op->ld = n;
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        hipError_t e = hipMemcpy2DAsync(op->K, n * sizeof(double), K, ld * sizeof(double), n * sizeof(double), n,
+                                        kind, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(op->M, n * sizeof(double), M, ld * sizeof(double), n * sizeof(double), n, kind,
+                                 c->stream);
+        if (e == hipSuccess && (flags & LREP_INPUT_AB)) e = combine_ab(c->stream, n, op->K, op->M);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->set_error(hipGetErrorString(e));
+            delete op;
+            return LREP_EDEVICE;
+        }
+    }
+    *out = op;
+    return LREP_OK;
+}
+
+int lrep_create_lowrank(lrep_ctx_t c, int64_t n, int64_t rank, const double* delta, const double* L, int64_t ldl,
+                        uint32_t flags, lrep_op_t* out) {
+    if (!c || !out || !delta || n < 1 || rank < 0 || (rank > 0 && (!L || ldl < n)) || n > (int64_t)INT32_MAX)
+        return LREP_EINVAL;
+    *out = nullptr;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    auto* op = new lrep_op_s();
+    op->ctx = c;
+    op->n = n;
+    op->kind = 1;
+    op->flags = flags;
+    op->rank = rank;
+    const bool dev = flags & LREP_DEVICE_PTR;
+    if (dev && (flags & LREP_BORROW)) {
+        op->delta = const_cast<double*>(delta);
+        op->L = const_cast<double*>(L);
+        op->ldl = ldl;
+    } else {
+        int rc = op->dbuf.alloc(c, n * sizeof(double));
+        if (rc == LREP_OK && rank > 0) rc = op->Lbuf.alloc(c, (size_t)n * rank * sizeof(double));
+        if (rc != LREP_OK) {
+            delete op;
+            return rc;
+        }
+        op->delta = op->dbuf.p;
+        op->L = op->Lbuf.p;
+        op->ldl = n;
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        hipError_t e = hipMemcpyAsync(op->delta, delta, n * sizeof(double), kind, c->stream);
+        if (e == hipSuccess && rank > 0)
+            e = hipMemcpy2DAsync(op->L, n * sizeof(double), L, ldl * sizeof(double), n * sizeof(double), rank, kind,
+                                 c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->set_error(hipGetErrorString(e));
+            delete op;
+            return LREP_EDEVICE;
+        }
+    }
+    *out = op;
+    return LREP_OK;
+}
+
+int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, int32_t on_device) {
+    if (!op || r < 0 || r >= op->n || (r > 0 && (!X0 || ld < op->n))) return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    op->r0 = 0;
+    op->X0.release();
+    op->Y0.release();
+    if (r == 0) return LREP_OK;
+    DevBuf tmp;
+    int rc = tmp.alloc(c, (size_t)op->n * r * sizeof(double));
+    if (rc != LREP_OK) return rc;
+    hipError_t e = hipMemcpy2DAsync(tmp.p, op->n * sizeof(double), X0, ld * sizeof(double), op->n * sizeof(double), r,
+                                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return LREP_EDEVICE;
+    rc = prepare_nullspace(op, c->stream, r, tmp.p);
+    if (rc != LREP_OK) {
+        op->r0 = 0;
+        op->X0.release();
+        op->Y0.release();
+    }
+    return rc;
+}
+
+int lrep_destroy_op(lrep_op_t op) {
+    if (!op) return LREP_EINVAL;
+    (void)set_device(op->ctx);
+    (void)hipStreamSynchronize(op->ctx->stream);
+    delete op;
+    return LREP_OK;
+}
+
+int lrep_solve(lrep_op_t op, int64_t n, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts,
+               double* lambda, double* X, double* Y, int64_t ldxy, lrep_stats_t* stats) {
+    if (!op) return LREP_EINVAL;
+    if (n != op->n) return LREP_EINVAL;
+    if (set_device(op->ctx) != LREP_OK) return LREP_EDEVICE;
+    return solve(op, op->ctx->stream, nev, block, tol, opts, lambda, X, Y, ldxy, stats);
+}
+
+int lrep_submit(lrep_ctx_t c, lrep_op_t op, const lrep_request_t* req, lrep_ticket_t* ticket) {
+    if (!c || !op || !req || !ticket || op->ctx != c) return LREP_EINVAL;
+    if (req->nev < 1 || req->block < 1 || !(req->tol > 0) || !req->lambda || !req->X || !req->Y ||
+        req->ldxy < op->n)
+        return LREP_EINVAL;
+    std::lock_guard<std::mutex> g(c->q_mu);
+    if (c->stopping) return LREP_EINVAL;
+    if (c->workers.empty()) {
+        c->n_workers = 4;
+        for (int i = 0; i < c->n_workers; ++i) c->workers.emplace_back(worker_main, c);
+    }
+    const uint64_t id = c->next_ticket++;
+    Ctx::Ticket t{};
+    t.op = op;
+    t.req = *req;
+    t.state = 0;
+    t.rc = LREP_EAGAIN;
+    c->tickets[id] = t;
+    c->queue.push_back(id);
+    *ticket = id;
+    c->q_cv.notify_all();
+    return LREP_OK;
+}
+
+int lrep_poll(lrep_ctx_t c, lrep_ticket_t ticket, lrep_stats_t* stats_out) {
+    if (!c) return LREP_EINVAL;
+    std::lock_guard<std::mutex> g(c->q_mu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return LREP_EINVAL;
+    if (it->second.state == 0 || it->second.state == 1) return LREP_EAGAIN;
+    const int rc = it->second.state == 3 ? LREP_ECANCELED : it->second.rc;
+    if (stats_out) *stats_out = it->second.stats;
+    c->tickets.erase(it);
+    return rc;
+}
+
+int lrep_cancel(lrep_ctx_t c, lrep_ticket_t ticket) {
+    if (!c) return LREP_EINVAL;
+    std::lock_guard<std::mutex> g(c->q_mu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return LREP_EINVAL;
+    if (it->second.state == 0) {
+        it->second.state = 3;
+        c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), ticket), c->queue.end());
+    }
+    return LREP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Library-internal objects behind the C ABI (lrep.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lrep.h"
+#include "kernels.hpp"
+
+namespace lrep {
+
+struct Ctx;
+
+// Device allocation charged against the context's HBM budget.
+struct DevBuf {
+    Ctx* ctx = nullptr;
+    double* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    int alloc(Ctx* c, size_t nbytes);   // LREP_OK / LREP_ENOMEM / LREP_EDEVICE
+    void release();
+};
+
+struct Op {
+    Ctx* ctx = nullptr;
+    int64_t n = 0;
+    int kind = 0;              // 0 dense, 1 low rank
+    uint32_t flags = 0;
+    // dense
+    double* K = nullptr;
+    double* M = nullptr;
+    int64_t ld = 0;
+    DevBuf Kbuf, Mbuf;
+    // low rank: K = diag(delta), M = diag(delta) + 2 L L^T
+    double* delta = nullptr;
+    double* L = nullptr;
+    int64_t rank = 0, ldl = 0;
+    DevBuf dbuf, Lbuf;
+    // generalized null space, biorthonormal X0^T Y0 = I (roles already exchanged)
+    int64_t r0 = 0;
+    DevBuf X0, Y0;
+    bool null_on_M() const { return (flags & LREP_NULL_ON_M) != 0; }
+};
+
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;         // 0: unlimited
+    std::atomic<size_t> used{0};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::mutex err_mu;
+    std::string last_error;
+    // serving
+    struct Ticket {
+        lrep_op_t op;
+        lrep_request_t req;
+        int state;             // 0 queued, 1 running, 2 done, 3 cancelled
+        int rc;
+        lrep_stats_t stats;
+    };
+    std::mutex q_mu;
+    std::condition_variable q_cv;
+    std::map<uint64_t, Ticket> tickets;
+    std::deque<uint64_t> queue;
+    uint64_t next_ticket = 1;
+    std::vector<std::thread> workers;
+    bool stopping = false;
+    int n_workers = 0;
+    void set_error(const std::string& s) {
+        std::lock_guard<std::mutex> g(err_mu);
+        last_error = s;
+    }
+};
+
+// Solver entry (solver.hip).  `st` is the stream the solve runs on.
+int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts,
+          double* lambda, double* X, double* Y, int64_t ldxy, lrep_stats_t* stats);
+
+// Null-space preparation (solver.hip): X0t (device, n x r, ld n) -> op->X0, op->Y0.
+int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);
+
+// Operator apply with the roles (after a possible exchange): which = 0 -> "K", 1 -> "M".
+int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy,
+             double* work, size_t work_elems, double* small, const int* active_flag);
+
+}  // namespace lrep

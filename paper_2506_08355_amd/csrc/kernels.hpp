@@ -1,0 +1,128 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+
+namespace lrep {
+
+constexpr int kMaxSeg = 4;
+constexpr int kMaxD = 128;     // largest subspace the one-workgroup small solver takes
+
+// A column segment of a larger logical matrix.
+struct Seg {
+    const double* p;
+    int64_t ld;
+    int cols;
+};
+
+// Status words written by kernels and read back by the driver.
+enum StatusSlot : int {
+    ST_NOTSPD = 0,       // Cholesky failure in the small problem
+    ST_NONFINITE = 1,    // NaN/Inf seen
+    ST_NKEPT = 2,        // columns kept by the last coefficient MGS
+    ST_NP = 3,           // columns of P^ kept by Step 5
+    ST_COUNT = 8
+};
+
+// Launchers taking `active_flag` skip all work when *active_flag == 0 (used
+// by the CG loop, which runs a fixed number of launches without host syncs).
+// ---- gemm.hip ------------------------------------------------------------
+hipError_t gemm_nn(hipStream_t st, int m, int q, int p, const Seg* A, int nsegA,
+                   const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
+                   double beta, double* work, size_t work_elems,
+                   const double* delta = nullptr, const double* Yd = nullptr,
+                   int64_t ldyd = 0, int ksplit_hint = 0, const int* active_flag = nullptr);
+
+hipError_t gemm_tn(hipStream_t st, int n, int p, int q, const Seg* A, int nsegA,
+                   const Seg* B, int nsegB, double* C, int64_t ldc, double alpha,
+                   int symmetrize, double* work, size_t work_elems,
+                   const int* active_flag = nullptr);
+
+// ---- vec.hip -------------------------------------------------------------
+// Y[:, j] = delta o X[:, j]
+hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      const int* active_flag = nullptr);
+
+// Step-4 residuals.  For Ritz columns j in [0, cols):
+//   eps[j] = sqrt(|KX_j - l_j Y_j|^2 + |MY_j - l_j X_j|^2) / ((1 + l_j) sqrt(|X_j|^2 + |Y_j|^2))
+// `part` holds (n/chunk) * cols * 4 doubles; `ticket` one unsigned (zeroed).
+hipError_t residual_eps(hipStream_t st, int n, int cols, const double* X, const double* Y,
+                        const double* KX, const double* MY, int64_t ld, const double* lam,
+                        double* eps, double* part, size_t part_elems, unsigned* ticket);
+
+// Block CG state for `w` independent systems A x_j = b_j (Step 6).
+struct CgState {
+    double *X, *R, *P, *Q;     // n x w, ld = n
+    double *rr, *bb, *alpha, *beta;   // w
+    int *active;               // w
+    int *any_active;           // 1
+    double* part;              // partial sums
+    size_t part_elems;
+    unsigned* ticket;          // 1
+    unsigned long long* napplies;   // running count of column applies (active columns)
+};
+// x = 0, r = p = b (B may alias R), rr = bb = |b|^2, active = rr > tol^2 bb
+hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb,
+                   double tol);
+// alpha_j = rr_j / (p_j . q_j) for active columns (p.q <= 0 stops the column)
+hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s);
+// x += alpha p, r -= alpha q, rr_new, beta, active update
+hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
+// p = r + beta p for active columns
+hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s);
+
+// Right-hand sides of the block Gauss-Seidel sweep (equation for the sweep):
+//   out[:, j] = lam[j] * (S[:, j] + T[:, g_j]) - U[:, g_j]
+// with g_j = win[j] indexing columns of T and U (S may be null = 0).
+hipError_t gs_rhs(hipStream_t st, int n, int w, const double* S, int64_t lds, const double* T,
+                  const double* U, int64_t ldt, const int* win, const double* lam_w,
+                  double* out, int64_t ldo);
+
+// out = in, column block copy with leading dimensions
+hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out,
+                     int64_t ldo);
+
+// max |S - I| over a d x d matrix (one workgroup); result into *out
+hipError_t max_offidentity(hipStream_t st, int d, const double* S, int64_t lds, double* out);
+
+// standard normal fill from the counter-based Philox4x32-10 generator
+// (Salmon, Moraes, Dror, Shaw, SC'11) with Box-Muller; element (i, j) uses
+// counter i + j * n so the block is independent of the launch shape.
+hipError_t philox_normal(hipStream_t st, int n, int cols, uint64_t seed, double* out, int64_t ld);
+
+// sign normalisation of returned pairs: x_j's entry of largest magnitude is
+// made positive, y_j flips with it.
+hipError_t sign_normalise(hipStream_t st, int n, int cols, double* X, double* Y, int64_t ld);
+
+// K <- A - B, M <- A + B element-wise (K holds A and M holds B on entry), n x n, ld n
+hipError_t combine_ab(hipStream_t st, int64_t n, double* K, double* M);
+
+// zero a column block
+hipError_t zero_cols(hipStream_t st, int n, int cols, double* X, int64_t ld);
+
+// ---- small.hip (one workgroup kernels on d x d data) ----------------------
+// Small structured LREP:  K^ = L1 L1^T, M^ = L2 L2^T, SVD of L1^T L2 by
+// one-sided Jacobi, all d Ritz pairs ascending: lam[d], Xh (d x d, ld kMaxD),
+// Yh.  `scratch` >= 3 * kMaxD * kMaxD doubles.  status[ST_NOTSPD] set on
+// Cholesky failure.
+hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh, int64_t ldh,
+                      double* lam, double* Xh, double* Yh, double* scratch, int* status);
+
+// Step 5 in coefficient space: for window Ritz indices win[0..nw):
+//   P^ = (I - Xk Yk^T)^2 (Xh[:, g] - e_g), Q^ likewise, Xk = Xh[:, 0:hi];
+// columns the projector annihilates are dropped, then MGS-Biorth (drop rule
+// of the oracle).  Writes P^, Q^ (d x np, ld kMaxD) and status[ST_NP] = np.
+hipError_t step5_pq(hipStream_t st, int d, int hi, const double* Xh, const double* Yh,
+                    const int* win, int nw, double* Ph, double* Qh, double* scratch,
+                    int* status, double cos_tol, double dep_tol);
+
+// Coefficient pass of block MGS-Biorth.  G is the Gram of [X Y] (2m x 2m,
+// ld ldg).  Runs the MGS-Biorth recurrence (Algorithm MGS-Biorth) on the
+// coefficient vectors: P = X A, Q = Y B with A, B upper triangular (m x m,
+// ld kMaxD; dropped columns compacted away).  status[ST_NKEPT] = kept count.
+hipError_t coef_mgs(hipStream_t st, int m, const double* G, int64_t ldg, double* A, double* B,
+                    int* status, double cos_tol, double dep_tol);
+
+}  // namespace lrep

@@ -1,0 +1,90 @@
+// Kernel-level entry points for the library's unit tests (include/lrep_testing.h).
+#include "../../include/lrep_testing.h"
+#include "internal.hpp"
+
+using namespace lrep;
+
+struct lrep_ctx_s : public Ctx {};
+struct lrep_op_s : public Op {};
+
+namespace lrep {
+int block_mgs_standalone(Ctx* c, hipStream_t st, int64_t n, int m, double* X, double* Y, int* kept);
+}
+
+namespace {
+int finish(Ctx* c, hipError_t e) {
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->set_error(hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    return LREP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lrep_test_gemm_nn(lrep_ctx_t ctx, int m, int q, int p, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, double alpha, double beta, int ksplit) {
+    if (!ctx || m < 0 || q < 0 || p < 0 || lda < m || ldb < p || ldc < m) return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    DevBuf work;
+    const size_t welems = (size_t)std::max(ksplit, 64) * m * q + 1;
+    int rc = work.alloc(ctx, welems * sizeof(double));
+    if (rc != LREP_OK) return rc;
+    Seg a{A, lda, p};
+    return finish(ctx, gemm_nn(ctx->stream, m, q, p, &a, 1, B, ldb, C, ldc, alpha, beta, work.p, welems, nullptr,
+                               nullptr, 0, ksplit));
+}
+
+int lrep_test_gemm_tn(lrep_ctx_t ctx, int n, int p, int q, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, int symmetrize) {
+    if (!ctx || n < 0 || p < 0 || q < 0 || lda < n || ldb < n || ldc < p) return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    DevBuf work;
+    const size_t welems = (size_t)1024 * p * q + 1;
+    int rc = work.alloc(ctx, welems * sizeof(double));
+    if (rc != LREP_OK) return rc;
+    Seg a{A, lda, p}, b{B, ldb, q};
+    return finish(ctx, gemm_tn(ctx->stream, n, p, q, &a, 1, &b, 1, C, ldc, 1.0, symmetrize, work.p, welems));
+}
+
+int lrep_test_small_lrep(lrep_ctx_t ctx, int d, const double* Kh, const double* Mh, int64_t ldh, double* lam,
+                         double* Xh, double* Yh) {
+    if (!ctx || d < 1 || d > kMaxD || ldh < d) return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    DevBuf scr, st;
+    int rc = scr.alloc(ctx, 3 * kMaxD * kMaxD * sizeof(double));
+    if (rc == LREP_OK) rc = st.alloc(ctx, ST_COUNT * sizeof(int));
+    if (rc != LREP_OK) return rc;
+    int* status = reinterpret_cast<int*>(st.p);
+    hipError_t e = hipMemsetAsync(status, 0, ST_COUNT * sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = small_lrep(ctx->stream, d, Kh, Mh, ldh, lam, Xh, Yh, scr.p, status);
+    rc = finish(ctx, e);
+    if (rc != LREP_OK) return rc;
+    int hs[ST_COUNT];
+    if (hipMemcpy(hs, status, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return LREP_EDEVICE;
+    return hs[ST_NOTSPD] ? LREP_ENOTSPD : LREP_OK;
+}
+
+int lrep_test_block_mgs(lrep_ctx_t ctx, int n, int m, double* X, double* Y, int* kept) {
+    if (!ctx || n < 1 || m < 0 || m > kMaxD || !kept) return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return block_mgs_standalone(ctx, ctx->stream, n, m, X, Y, kept);
+}
+
+int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* Y) {
+    if (!op || cols < 0 || (which != 0 && which != 1)) return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    (void)hipSetDevice(c->device);
+    DevBuf work, small;
+    const size_t welems = size_t(8) << 20;
+    int rc = work.alloc(c, welems * sizeof(double));
+    if (rc == LREP_OK) rc = small.alloc(c, (size_t)std::max<int64_t>(op->rank, 1) * std::max(cols, 1) * sizeof(double));
+    if (rc != LREP_OK) return rc;
+    rc = op_apply(op, c->stream, which, X, op->n, cols, Y, op->n, work.p, welems, small.p, nullptr);
+    if (rc != LREP_OK) return rc;
+    return finish(c, hipSuccess);
+}
+
+}  // extern "C"

@@ -1,0 +1,417 @@
+// Streaming (HBM-bound) kernels of the BOSP iteration on gfx950: fused
+// residual norms (Step 4), the block CG of Step 6, right-hand sides of the
+// block Gauss-Seidel sweep, and small utilities.  Every reduction is two
+// stage with a fixed summation order (bitwise reproducible).
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace lrep {
+
+namespace {
+constexpr int NT = 256;
+
+inline int chunks_for(int n, int cols, int rows_per_block = 4096, int max_chunks = 256) {
+    int c = (n + rows_per_block - 1) / rows_per_block;
+    // keep at least ~512 workgroups in flight when the problem is big enough
+    while (c * cols < 512 && c < max_chunks && (n + 2 * c - 1) / (2 * c) >= 1024) c *= 2;
+    return std::max(1, std::min(c, max_chunks));
+}
+
+__global__ __launch_bounds__(NT) void diag_scale_kernel(int n, int cols, const double* __restrict__ delta,
+                                                        const double* __restrict__ X, int64_t ldx,
+                                                        double* __restrict__ Y, int64_t ldy,
+                                                        const int* __restrict__ active_flag) {
+    if (active_flag && *active_flag == 0) return;
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        Y[(int64_t)j * ldy + i] = delta[i] * X[(int64_t)j * ldx + i];
+}
+
+// ---------------------------------------------------------------- residuals
+__global__ __launch_bounds__(NT) void residual_kernel(int n, int cols, int nchunks, const double* __restrict__ X,
+                                                      const double* __restrict__ Y, const double* __restrict__ KX,
+                                                      const double* __restrict__ MY, int64_t ld,
+                                                      const double* __restrict__ lam, double* __restrict__ eps,
+                                                      double* __restrict__ part, unsigned* ticket) {
+    __shared__ double red[NT / WAVE];
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const double l = lam[j];
+    const int64_t off = (int64_t)j * ld;
+    double s1 = 0, s2 = 0, sx = 0, sy = 0;
+    for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+        const double x = X[off + i], y = Y[off + i];
+        const double a = KX[off + i] - l * y;
+        const double b = MY[off + i] - l * x;
+        s1 += a * a;
+        s2 += b * b;
+        sx += x * x;
+        sy += y * y;
+    }
+    s1 = block_sum<NT>(s1, red);
+    s2 = block_sum<NT>(s2, red);
+    sx = block_sum<NT>(sx, red);
+    sy = block_sum<NT>(sy, red);
+    if (threadIdx.x == 0) {
+        double* p = part + ((int64_t)j * nchunks + ch) * 4;
+        p[0] = s1;
+        p[1] = s2;
+        p[2] = sx;
+        p[3] = sy;
+    }
+    if (last_block_arrives(ticket, gridDim.x * gridDim.y)) {
+        for (int c = threadIdx.x; c < cols; c += NT) {
+            double t1 = 0, t2 = 0, tx = 0, ty = 0;
+            const double* p = part + (int64_t)c * nchunks * 4;
+            for (int k = 0; k < nchunks; ++k) {
+                t1 += p[4 * k];
+                t2 += p[4 * k + 1];
+                tx += p[4 * k + 2];
+                ty += p[4 * k + 3];
+            }
+            const double lc = lam[c];
+            eps[c] = sqrt(t1 + t2) / ((1.0 + lc) * sqrt(tx + ty));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- CG
+__global__ __launch_bounds__(NT) void cg_init_kernel(int n, int w, int nchunks, CgState s,
+                                                     const double* __restrict__ B, int64_t ldb, double tol) {
+    __shared__ double red[NT / WAVE];
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+        const double b = B[(int64_t)j * ldb + i];
+        s.X[off + i] = 0.0;
+        s.R[off + i] = b;
+        s.P[off + i] = b;
+        acc += b * b;
+    }
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
+        __shared__ int any;
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < w; c += NT) {
+            double t = 0;
+            for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
+            s.rr[c] = t;
+            s.bb[c] = t;
+            const int a = t > tol * tol * t ? 1 : 0;
+            s.active[c] = a;
+            if (a) atomicOr(&any, 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *s.any_active = any;
+    }
+}
+
+__global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks, CgState s) {
+    __shared__ double red[NT / WAVE];
+    if (*s.any_active == 0) return;
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    if (s.active[j])
+        for (int i = r0 + threadIdx.x; i < r1; i += NT) acc += s.P[off + i] * s.Q[off + i];
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
+        if (threadIdx.x == 0) {
+            unsigned long long na = 0;
+            for (int c = 0; c < w; ++c) na += s.active[c] ? 1ull : 0ull;
+            *s.napplies += na;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < w; c += NT) {
+            double a = 0.0;
+            if (s.active[c]) {
+                double pq = 0;
+                for (int k = 0; k < nchunks; ++k) pq += s.part[(int64_t)c * nchunks + k];
+                if (pq > 0.0)
+                    a = s.rr[c] / pq;
+                else
+                    s.active[c] = 0;   // breakdown: p^T A p <= 0 (singular operator)
+            }
+            s.alpha[c] = a;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol) {
+    __shared__ double red[NT / WAVE];
+    if (*s.any_active == 0) return;
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    if (s.active[j]) {
+        const double a = s.alpha[j];
+        for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+            s.X[off + i] += a * s.P[off + i];
+            const double r = s.R[off + i] - a * s.Q[off + i];
+            s.R[off + i] = r;
+            acc += r * r;
+        }
+    }
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
+        __shared__ int any;
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < w; c += NT) {
+            if (s.active[c]) {
+                double t = 0;
+                for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
+                s.beta[c] = t / s.rr[c];
+                s.rr[c] = t;
+                const int a = t > tol * tol * s.bb[c] ? 1 : 0;
+                s.active[c] = a;
+                if (a) atomicOr(&any, 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *s.any_active = any;
+    }
+}
+
+__global__ __launch_bounds__(NT) void cg_direction_kernel(int n, int w, CgState s) {
+    if (*s.any_active == 0) return;
+    const int j = blockIdx.y;
+    if (!s.active[j]) return;
+    const double b = s.beta[j];
+    const int64_t off = (int64_t)j * n;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        s.P[off + i] = s.R[off + i] + b * s.P[off + i];
+}
+
+__global__ __launch_bounds__(NT) void gs_rhs_kernel(int n, const double* __restrict__ S, int64_t lds,
+                                                    const double* __restrict__ T, const double* __restrict__ U,
+                                                    int64_t ldt, const int* __restrict__ win,
+                                                    const double* __restrict__ lam_w, double* __restrict__ out,
+                                                    int64_t ldo) {
+    const int j = blockIdx.y;
+    const int g = win[j];
+    const double l = lam_w[j];
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const double sv = S ? S[(int64_t)j * lds + i] : 0.0;
+        out[(int64_t)j * ldo + i] = l * (sv + T[(int64_t)g * ldt + i]) - U[(int64_t)g * ldt + i];
+    }
+}
+
+__global__ __launch_bounds__(NT) void copy_cols_kernel(int n, const double* __restrict__ in, int64_t ldi,
+                                                       double* __restrict__ out, int64_t ldo) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        out[(int64_t)j * ldo + i] = in[(int64_t)j * ldi + i];
+}
+
+__global__ __launch_bounds__(NT) void zero_cols_kernel(int n, double* __restrict__ X, int64_t ld) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) X[(int64_t)j * ld + i] = 0.0;
+}
+
+__global__ __launch_bounds__(1024) void max_offidentity_kernel(int d, const double* __restrict__ S, int64_t lds,
+                                                               double* out) {
+    __shared__ double red[1024 / WAVE];
+    double m = 0.0;
+    for (int idx = threadIdx.x; idx < d * d; idx += 1024) {
+        const int i = idx % d, j = idx / d;
+        const double v = S[(int64_t)j * lds + i] - (i == j ? 1.0 : 0.0);
+        m = fmax(m, fabs(v));
+        if (!(v == v)) m = INFINITY;   // NaN -> force a restore / error path
+    }
+    m = wave_max(m);
+    const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+    if (lane == 0) red[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 1024 / WAVE; ++i) t = fmax(t, red[i]);
+        *out = t;
+    }
+}
+
+// Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3", SC'11)
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)M0 * c[0];
+        const uint64_t p1 = (uint64_t)M1 * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+__global__ __launch_bounds__(NT) void philox_normal_kernel(int n, uint64_t seed, double* __restrict__ out,
+                                                           int64_t ld) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const uint64_t ctr = (uint64_t)i + (uint64_t)j * (uint64_t)n;
+        uint32_t c[4] = {(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u};
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+        const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6)) * (1.0 / 9007199254740992.0);
+        out[(int64_t)j * ld + i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+__global__ __launch_bounds__(NT) void sign_normalise_kernel(int n, double* __restrict__ X, double* __restrict__ Y,
+                                                            int64_t ld) {
+    __shared__ double sv[NT];
+    __shared__ int si[NT];
+    const int j = blockIdx.x;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    double sgn = 1.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const double v = X[(int64_t)j * ld + i];
+        const double a = fabs(v);
+        if (a > best) {
+            best = a;
+            bi = i;
+            sgn = v < 0 ? -1.0 : 1.0;
+        }
+    }
+    sv[threadIdx.x] = best * sgn;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double a = fabs(sv[threadIdx.x]), b = fabs(sv[threadIdx.x + s]);
+            if (b > a || (b == a && si[threadIdx.x + s] < si[threadIdx.x])) {
+                sv[threadIdx.x] = sv[threadIdx.x + s];
+                si[threadIdx.x] = si[threadIdx.x + s];
+            }
+        }
+        __syncthreads();
+    }
+    const double f = sv[0] < 0 ? -1.0 : 1.0;
+    if (f < 0)
+        for (int i = threadIdx.x; i < n; i += NT) {
+            X[(int64_t)j * ld + i] = -X[(int64_t)j * ld + i];
+            Y[(int64_t)j * ld + i] = -Y[(int64_t)j * ld + i];
+        }
+}
+
+__global__ __launch_bounds__(NT) void combine_ab_kernel(int64_t total, double* __restrict__ K, double* __restrict__ M) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
+        const double a = K[i], b = M[i];
+        K[i] = a - b;
+        M[i] = a + b;
+    }
+}
+
+inline dim3 grid_rows(int n, int cols, int max_x = 1024) {
+    return dim3(std::max(1, std::min(max_x, (n + NT - 1) / NT)), cols);
+}
+}  // namespace
+
+hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy, const int* active_flag) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(diag_scale_kernel, grid_rows(n, cols, 512), dim3(NT), 0, st, n, cols, delta, X, ldx, Y, ldy,
+                       active_flag);
+    return hipGetLastError();
+}
+
+hipError_t residual_eps(hipStream_t st, int n, int cols, const double* X, const double* Y, const double* KX,
+                        const double* MY, int64_t ld, const double* lam, double* eps, double* part,
+                        size_t part_elems, unsigned* ticket) {
+    if (cols <= 0) return hipSuccess;
+    int nch = chunks_for(n, cols);
+    while ((size_t)nch * cols * 4 > part_elems && nch > 1) nch /= 2;
+    hipLaunchKernelGGL(residual_kernel, dim3(nch, cols), dim3(NT), 0, st, n, cols, nch, X, Y, KX, MY, ld, lam, eps,
+                       part, ticket);
+    return hipGetLastError();
+}
+
+static int cg_chunks(int n, int w, const CgState& s) {
+    int nch = chunks_for(n, w);
+    while ((size_t)nch * w > s.part_elems && nch > 1) nch /= 2;
+    return nch;
+}
+
+hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb, double tol) {
+    const int nch = cg_chunks(n, w, s);
+    hipLaunchKernelGGL(cg_init_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, B, ldb, tol);
+    return hipGetLastError();
+}
+hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
+    const int nch = cg_chunks(n, w, s);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s);
+    return hipGetLastError();
+}
+hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol) {
+    const int nch = cg_chunks(n, w, s);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, tol);
+    return hipGetLastError();
+}
+hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s) {
+    hipLaunchKernelGGL(cg_direction_kernel, grid_rows(n, w, 256), dim3(NT), 0, st, n, w, s);
+    return hipGetLastError();
+}
+
+hipError_t gs_rhs(hipStream_t st, int n, int w, const double* S, int64_t lds, const double* T, const double* U,
+                  int64_t ldt, const int* win, const double* lam_w, double* out, int64_t ldo) {
+    if (w <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gs_rhs_kernel, grid_rows(n, w, 256), dim3(NT), 0, st, n, S, lds, T, U, ldt, win, lam_w, out,
+                       ldo);
+    return hipGetLastError();
+}
+
+hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out, int64_t ldo) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, in, ldi, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t combine_ab(hipStream_t st, int64_t n, double* K, double* M) {
+    const int64_t total = n * n;
+    hipLaunchKernelGGL(combine_ab_kernel, dim3((unsigned)std::min<int64_t>(8192, (total + NT - 1) / NT)), dim3(NT), 0,
+                       st, total, K, M);
+    return hipGetLastError();
+}
+
+hipError_t zero_cols(hipStream_t st, int n, int cols, double* X, int64_t ld) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, X, ld);
+    return hipGetLastError();
+}
+
+hipError_t max_offidentity(hipStream_t st, int d, const double* S, int64_t lds, double* out) {
+    hipLaunchKernelGGL(max_offidentity_kernel, dim3(1), dim3(1024), 0, st, d, S, lds, out);
+    return hipGetLastError();
+}
+
+hipError_t philox_normal(hipStream_t st, int n, int cols, uint64_t seed, double* out, int64_t ld) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_normal_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, seed, out, ld);
+    return hipGetLastError();
+}
+
+hipError_t sign_normalise(hipStream_t st, int n, int cols, double* X, double* Y, int64_t ld) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sign_normalise_kernel, dim3(cols), dim3(NT), 0, st, n, X, Y, ld);
+    return hipGetLastError();
+}
+
+}  // namespace lrep

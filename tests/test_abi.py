@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every symbol its headers declare
+(no compute calls: these run without a GPU)."""
+import ctypes
+
+import pytest
+
+import paper_2506_08355_amd as L
+
+
+def test_library_exports_declared_symbols():
+    lib = L.lib()
+    names = L.declared_symbols()
+    assert "lrep_solve" in names and "lrep_submit" in names and "lrep_poll" in names
+    assert "lrep_create_dense" in names and "lrep_create_lowrank" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version():
+    assert L.lrep_version() == 100
+    for code in range(0, -10, -1):
+        assert L.lrep_strerror(code)
+    assert L.lrep_strerror(-123) == "unknown error"
+
+
+def test_invalid_arguments_are_rejected_without_device_work():
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    assert lib.lrep_init(None, 0, 0, None) == L.LREP_EINVAL
+    assert lib.lrep_init(ctypes.byref(h), -1, 0, None) == L.LREP_EINVAL
+    assert lib.lrep_finalize(None) == L.LREP_EINVAL
+    assert lib.lrep_solve(None, 1, 1, 1, 1e-8, None, None, None, None, 1, None) == L.LREP_EINVAL
+    assert lib.lrep_poll(None, 1, None) == L.LREP_EINVAL
+    assert lib.lrep_destroy_op(None) == L.LREP_EINVAL
+
+
+def test_binding_layout_checks():
+    import numpy as np
+    with pytest.raises(ValueError):
+        L.colmajor(np.zeros((4, 3)))          # C order
+    p, ld, dev = L.colmajor(np.zeros((4, 3), order="F"))
+    assert ld == 4 and not dev
+    torch = pytest.importorskip("torch")
+    t = torch.zeros(3, 5, dtype=torch.float64).T
+    p, ld, dev = L.colmajor(t)
+    assert ld == 5 and not dev

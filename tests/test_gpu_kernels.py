@@ -1,0 +1,156 @@
+"""Kernel-level GPU tests through the testing entry points of the C ABI,
+against plain FP64 NumPy (and the oracle's small LREP / MGS-Biorth)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2506_08355_amd as L
+from gpu_util import dev_colmajor, dev_empty, host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    c = L.lrep_init(0)
+    yield c
+    L.lrep_finalize(c)
+
+
+@pytest.mark.parametrize("m,p,q,ksplit,beta", [
+    (16, 4, 16, 0, 0.0), (300, 257, 33, 0, 0.0), (1000, 1000, 32, 4, 0.0), (129, 48, 16, 0, 0.5),
+    (517, 130, 100, 0, 0.0), (4096, 4096, 32, 0, 0.0), (2048, 2048, 128, 0, 0.0)])
+def test_gemm_nn(ctx, m, p, q, ksplit, beta):
+    rng = np.random.default_rng(m + p + q)
+    A = rng.standard_normal((m, p))
+    B = rng.standard_normal((p, q))
+    C0 = rng.standard_normal((m, q))
+    Ad, Bd, Cd = dev_colmajor(A, torch), dev_colmajor(B, torch), dev_colmajor(C0, torch)
+    torch.cuda.synchronize()
+    L.lrep_test_gemm_nn(ctx, Ad, Bd, Cd, alpha=1.5, beta=beta, ksplit=ksplit)
+    ref = 1.5 * A @ B + beta * C0
+    scale = np.sqrt(max(p, 1)) * 4
+    np.testing.assert_allclose(host(Cd), ref, atol=1e-14 * scale * 8, rtol=0)
+
+
+@pytest.mark.parametrize("n,p,q,sym", [(64, 16, 16, False), (5000, 70, 33, False), (8192, 128, 128, True),
+                                       (100003, 32, 64, False), (3, 5, 7, False)])
+def test_gemm_tn(ctx, n, p, q, sym):
+    rng = np.random.default_rng(n + p)
+    A = rng.standard_normal((n, p))
+    B = A[:, :q] + 0.1 * rng.standard_normal((n, q)) if sym else rng.standard_normal((n, q))
+    Cd = dev_empty(p, q, torch)
+    L.lrep_test_gemm_tn(ctx, dev_colmajor(A, torch), dev_colmajor(B, torch), Cd, symmetrize=sym)
+    ref = A.T @ B
+    if sym:
+        ref = 0.5 * (ref + ref.T)
+    np.testing.assert_allclose(host(Cd), ref, atol=1e-13 * np.sqrt(n) * 4, rtol=0)
+
+
+def _spd(rng, d, cond):
+    q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    return (q * np.geomspace(1.0, cond, d)) @ q.T
+
+
+@pytest.mark.parametrize("d,cond", [(1, 1.0), (10, 10.0), (30, 1e3), (48, 1e4), (64, 1e2), (100, 1e3), (128, 1e5)])
+def test_small_lrep_against_oracle(ctx, d, cond):
+    rng = np.random.default_rng(d)
+    Kh, Mh = _spd(rng, d, cond), _spd(rng, d, cond)
+    lam = torch.zeros(d, dtype=torch.float64, device="cuda:0")
+    Xh = dev_empty(128, 128, torch)
+    Yh = dev_empty(128, 128, torch)
+    rc = L.lrep_test_small_lrep(ctx, dev_colmajor(Kh, torch), dev_colmajor(Mh, torch), lam, Xh, Yh)
+    assert rc == L.LREP_OK
+    lam_h, X, Y = host(lam), host(Xh)[:d, :d], host(Yh)[:d, :d]
+    ref, _, _ = oracle.small_lrep(Kh, Mh, d)
+    np.testing.assert_allclose(lam_h, ref, rtol=1e-12 * cond)
+    np.testing.assert_allclose(X.T @ Y, np.eye(d), atol=1e-12 * cond)
+    scale = np.abs(Kh).max() + np.abs(Mh).max()
+    assert np.abs(Kh @ X - Y * lam_h).max() <= 1e-11 * scale * max(np.abs(X).max(), 1)
+    assert np.abs(Mh @ Y - X * lam_h).max() <= 1e-11 * scale * max(np.abs(Y).max(), 1)
+
+
+def test_small_lrep_reports_not_spd(ctx):
+    d = 6
+    Kh = np.diag([1.0, 2.0, -1.0, 3.0, 1.0, 1.0])
+    lam = torch.zeros(d, dtype=torch.float64, device="cuda:0")
+    Xh, Yh = dev_empty(128, 128, torch), dev_empty(128, 128, torch)
+    rc = L.lrep_test_small_lrep(ctx, dev_colmajor(Kh, torch), dev_colmajor(np.eye(d), torch), lam, Xh, Yh)
+    assert rc == L.LREP_ENOTSPD
+
+
+@pytest.mark.parametrize("n,m,same", [(200, 7, True), (5000, 32, False), (3000, 128, True), (1000, 48, False)])
+def test_block_mgs_biorth(ctx, n, m, same):
+    rng = np.random.default_rng(n + m)
+    X = rng.standard_normal((n, m))
+    Y = X.copy() if same else X + 0.5 * rng.standard_normal((n, m))
+    Xd, Yd = dev_colmajor(X, torch).T.contiguous().T, dev_colmajor(Y, torch).T.contiguous().T
+    k = L.lrep_test_block_mgs(ctx, Xd, Yd)
+    assert k == m
+    P, Q = host(Xd)[:, :k], host(Yd)[:, :k]
+    np.testing.assert_allclose(P.T @ Q, np.eye(m), atol=1e-12)
+    # same spans as the inputs (X = P R with R upper triangular)
+    R = Q.T @ X
+    np.testing.assert_allclose(np.tril(R, -1), 0, atol=1e-10 * np.abs(R).max())
+    if same:                      # MGS-Biorth with Y = X is MGS orthogonalisation
+        q, r = np.linalg.qr(X)
+        q *= np.sign(np.diag(r))
+        np.testing.assert_allclose(P, q, atol=1e-12)
+    Po, Qo, kept = oracle.mgs_biorth(X, Y)
+    np.testing.assert_allclose(P, Po, atol=1e-9 * np.abs(Po).max())
+    np.testing.assert_allclose(Q, Qo, atol=1e-9 * np.abs(Qo).max())
+
+
+def test_block_mgs_drops_dependent_columns(ctx):
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((500, 6))
+    X[:, 3] = X[:, 0] - 2 * X[:, 1]
+    Xd = dev_colmajor(X, torch).T.contiguous().T
+    Yd = Xd.clone().T.contiguous().T
+    k = L.lrep_test_block_mgs(ctx, Xd, Yd)
+    assert k == 5
+    P, Q = host(Xd)[:, :k], host(Yd)[:, :k]
+    np.testing.assert_allclose(P.T @ Q, np.eye(5), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank", "dense_swap"])
+def test_operator_apply(ctx, kind):
+    rng = np.random.default_rng(5)
+    n, cols = 1500, 19
+    Xh = rng.standard_normal((n, cols))
+    if kind == "lowrank":
+        f = gen.casida_factors(n, 24, 3)
+        op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+        K, M = f.K(), f.M()
+    else:
+        K, M, _ = gen.dense_operator(n, 4)
+        flags = L.LREP_NULL_ON_M if kind == "dense_swap" else 0
+        op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), flags)
+        if kind == "dense_swap":
+            K, M = M, K
+    Xd = dev_colmajor(Xh, torch).T.contiguous().T
+    Yd = dev_empty(n, cols, torch).T.contiguous().T
+    for which, A in ((0, K), (1, M)):
+        L.lrep_test_apply(op, which, Xd, Yd)
+        np.testing.assert_allclose(host(Yd), A @ Xh, atol=1e-12 * np.abs(A @ Xh).max())
+    L.lrep_destroy_op(op)
+
+
+def test_input_ab_forms_k_and_m(ctx):
+    rng = np.random.default_rng(8)
+    n = 200
+    A = rng.standard_normal((n, n)); A = A + A.T
+    B = rng.standard_normal((n, n)); B = B + B.T
+    op = L.lrep_create_dense(ctx, dev_colmajor(A, torch), dev_colmajor(B, torch), L.LREP_INPUT_AB)
+    X = rng.standard_normal((n, 3))
+    Xd = dev_colmajor(X, torch).T.contiguous().T
+    Yd = dev_empty(n, 3, torch).T.contiguous().T
+    L.lrep_test_apply(op, 0, Xd, Yd)
+    np.testing.assert_allclose(host(Yd), (A - B) @ X, atol=1e-11)
+    L.lrep_test_apply(op, 1, Xd, Yd)
+    np.testing.assert_allclose(host(Yd), (A + B) @ X, atol=1e-11)
+    L.lrep_destroy_op(op)

@@ -1,0 +1,164 @@
+"""Parity of the GPU solver (through the C ABI) with the FP64 CPU oracle on
+the same seeded inputs and the same starting block.
+
+Bars (from the build's accuracy contract):
+  eigenvalues       |lambda_gpu - lambda_oracle| / lambda_oracle <= 1e-10
+  residual          ||H z - lambda z|| / (||H|| ||z||) <= 1e-8, z = [y; x]
+  biorthogonality   max |Y^T X - I| <= 1e-12 (looser where the paper's own
+                    problem bounds it: eps ||H|| / lambda_min for tiny lambda)
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2506_08355_amd as L
+from oracle import exact
+from conftest import load_golden
+from gpu_util import dev_colmajor, h_residual
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    c = L.lrep_init(0)
+    yield c
+    L.lrep_finalize(c)
+
+
+def gpu_solve(ctx, op, n, nev, block, tol, window=0, init=None, **kw):
+    lam = np.zeros(nev)
+    X = np.zeros((n, nev), order="F")
+    Y = np.zeros((n, nev), order="F")
+    opts = L.make_opts(window=window, init=None if init is None else np.asfortranarray(init), **kw)
+    rc, st = L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx, check=False)
+    return rc, st, lam, X, Y
+
+
+def check_pair(lam, X, Y, ref_lam, K_apply, M_apply, normH, bi_tol=1e-12, lam_tol=1e-10):
+    np.testing.assert_allclose(lam, ref_lam, rtol=lam_tol, atol=0)
+    res = h_residual(K_apply, M_apply, X, Y, lam, normH)
+    assert res.max() <= 1e-8, res.max()
+    k = lam.size
+    assert np.abs(X.T @ Y - np.eye(k)).max() <= bi_tol
+    return res
+
+
+def test_config1_dense_n256(ctx):
+    n, nev, block, tol = 256, 8, 16, 1e-10
+    K, M, f = gen.dense_operator(n, 1001)
+    U, _ = gen.init_block(n, 3 * block, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    ref = oracle.bosp_solve(oracle.DenseOperator(K, M), nev, block, tol, init=(U, U))
+    check_pair(lam, X, Y, ref.lam, lambda v: K @ v, lambda v: M @ v, f.norm_H())
+    np.testing.assert_allclose(lam, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev), rtol=1e-10)
+    # same eigenvectors as the oracle (both sign-normalised; spectrum is simple here)
+    np.testing.assert_allclose(X, ref.X, atol=1e-7 * np.abs(ref.X).max())
+    np.testing.assert_allclose(Y, ref.Y, atol=1e-7 * np.abs(ref.Y).max())
+    assert st.n_converged == nev and st.max_eps <= tol
+
+
+def test_config1_default_start_block(ctx):
+    """The library's own Philox starting block reaches the same eigenpairs."""
+    n, nev, block, tol = 256, 8, 16, 1e-10
+    K, M, f = gen.dense_operator(n, 1001)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, seed=12345)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    check_pair(lam, X, Y, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev), lambda v: K @ v, lambda v: M @ v,
+               f.norm_H())
+
+
+def test_example_4_1(ctx):
+    n = 1000
+    T0 = gen.tridiag_T(n, 0.0)
+    U, _ = gen.init_block(n, 30, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(T0, torch), dev_colmajor(T0, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, 10, 10, 1e-10, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    printed = load_golden("example_4_1_eigenvalues.txt")[:, 1]
+    # tiny eigenvalues (1e-5 against ||H|| = 4): X^T Y = I holds to ~ eps ||H|| / lambda_1
+    check_pair(lam, X, Y, printed, lambda v: T0 @ v, lambda v: T0 @ v, 4.0, bi_tol=1e-10)
+
+
+def test_example_4_2_nullspace(ctx):
+    n = 1000
+    K = gen.tridiag_T(n, -1.0)
+    M = gen.tridiag_T(n, 0.0)
+    U, _ = gen.init_block(n, 30, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    L.lrep_set_nullspace(op, np.ones((n, 1)), ctx)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, 10, 10, 1e-10, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    printed = load_golden("example_4_2_eigenvalues.txt")[:, 1]
+    check_pair(lam, X, Y, printed, lambda v: K @ v, lambda v: M @ v, 4.0, bi_tol=1e-10)
+    # Lemma 2.3 (iii): biorthogonal to the generalized null space
+    y0 = M @ np.ones(n)
+    y0 = np.linalg.solve(M, np.ones(n))
+    assert np.abs(y0 @ X).max() <= 1e-9 * np.linalg.norm(y0) * np.abs(X).max() * np.sqrt(n)
+    assert np.abs(np.ones(n) @ Y).max() <= 1e-9 * np.sqrt(n) * np.abs(Y).max()
+
+
+def test_zero_variant_role_swap_moving(ctx):
+    n, nev, block, window, tol = 400, 24, 16, 8, 1e-10
+    K, M, f = gen.dense_operator(n, 1012, n_zero_m=8)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), L.LREP_NULL_ON_M)
+    L.lrep_set_nullspace(op, np.asfortranarray(f.null_basis_M()), ctx)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    assert st.locks >= 1
+    ref = oracle.bosp_solve(oracle.DenseOperator(K, M), nev, block, tol, window=window, init=(U, U),
+                            X0=f.null_basis_M(), null_on_M=True)
+    check_pair(lam, X, Y, ref.lam, lambda v: K @ v, lambda v: M @ v, f.norm_H())
+    np.testing.assert_allclose(lam, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev), rtol=1e-10)
+    assert np.abs(f.null_basis_M().T @ X).max() <= 1e-10
+
+
+def test_casida_lowrank_moving(ctx):
+    n, r, nev, block, window, tol = 1500, 16, 32, 16, 8, 1e-9
+    f = gen.casida_factors(n, r, 1003)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    cop = oracle.CasidaOperator(f.delta, f.L)
+    ref = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U, U))
+    normH = np.linalg.norm(f.M(), 2)
+    check_pair(lam, X, Y, ref.lam, cop.apply_K, cop.apply_M, normH)
+    assert exact.casida_count_below(f.delta, f.L, lam[-1] * (1 + 1e-9)) == nev
+
+
+def test_error_paths(ctx):
+    n = 64
+    K, M, f = gen.dense_operator(n, 3)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    # block too large for the device's small solver
+    rc, *_ = gpu_solve(ctx, op, n, 4, 60, 1e-8)
+    assert rc == L.LREP_EINVAL
+    # n mismatch
+    lam = np.zeros(4); X = np.zeros((n, 4), order="F"); Y = np.zeros((n, 4), order="F")
+    rc, _ = L.lrep_solve(op, n + 1, 4, 4, 1e-8, L.make_opts(), lam, X, Y, check=False)
+    assert rc == L.LREP_EINVAL
+    # maxit reached: converged prefix only
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, 4, 4, 1e-14, maxit=2)
+    assert rc == L.LREP_ENOTCONV and st.iterations == 2
+    L.lrep_destroy_op(op)
+    # NaN in the operator
+    Kn = K.copy(); Kn[3, 5] = np.nan
+    op = L.lrep_create_dense(ctx, dev_colmajor(Kn, torch), dev_colmajor(M, torch))
+    rc, *_ = gpu_solve(ctx, op, n, 4, 4, 1e-8)
+    assert rc in (L.LREP_ENUMERIC, L.LREP_ENOTSPD)
+    L.lrep_destroy_op(op)
