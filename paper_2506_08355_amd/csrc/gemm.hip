@@ -15,7 +15,7 @@
 // Every matrix is column-major FP64.  Lane layout of the 16x16x4 FP64 MFMA:
 //   A (16x4):  lane l holds A[l % 16][l / 16]
 //   B (4x16):  lane l holds B[l / 16][l % 16]
-//   D (16x16): lane l holds D[4 * (l / 16) + r][l % 16], r = 0..3
+//   D (16x16): lane l holds D[4 * r + l / 16][l % 16] in item r = 0..3
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(NT) void gemm_nn_kernel(
             if (c >= q) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wm * TM + i * 16 + 4 * (lane / 16) + r;
+                const int row = row0 + wm * TM + i * 16 + 4 * r + lane / 16;
                 if (row >= m) continue;
                 const double v = acc[i][j][r];
                 if (part) {
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(NT) void gemm_tn_kernel(
             const int c = d0 + wn * TN + j * 16 + lane % 16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = c0 + wm * TM + i * 16 + 4 * (lane / 16) + r;
+                const int row = c0 + wm * TM + i * 16 + 4 * r + lane / 16;
                 if (row < p && c < q) part[((int64_t)s * q + c) * p + row] = acc[i][j][r];
             }
         }

@@ -102,11 +102,10 @@ def test_example_4_2_nullspace(ctx):
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     printed = load_golden("example_4_2_eigenvalues.txt")[:, 1]
     check_pair(lam, X, Y, printed, lambda v: K @ v, lambda v: M @ v, 4.0, bi_tol=1e-10)
-    # Lemma 2.3 (iii): biorthogonal to the generalized null space
-    y0 = M @ np.ones(n)
-    y0 = np.linalg.solve(M, np.ones(n))
-    assert np.abs(y0 @ X).max() <= 1e-9 * np.linalg.norm(y0) * np.abs(X).max() * np.sqrt(n)
-    assert np.abs(np.ones(n) @ Y).max() <= 1e-9 * np.sqrt(n) * np.abs(Y).max()
+    # Lemma 2.3 (iii): biorthogonal to the generalized null space (X0^T Y0 = I basis)
+    X0, Y0 = oracle.nullspace_basis(np.ones((n, 1)), oracle.DenseOperator(K, M).solve_M)
+    assert np.abs(Y0.T @ X).max() <= 1e-10 * np.linalg.norm(Y0) * np.abs(X).max() * n
+    assert np.abs(X0.T @ Y).max() <= 1e-11
 
 
 def test_zero_variant_role_swap_moving(ctx):
