@@ -43,6 +43,7 @@ __all__ = [
     "init_block",
     "DenseFactors",
     "CasidaFactors",
+    "dense_operator_device",
 ]
 
 
@@ -166,3 +167,32 @@ def init_block(n: int, d: int, seed: int):
     U = np.asfortranarray(rng.standard_normal((d, n)).T)
     V = np.asfortranarray(rng.standard_normal((d, n)).T)
     return U, V
+
+
+def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
+                          lo: float = 0.5, hi: float = 10.0):
+    """The dense workload built on a torch device: the same NumPy draws in the
+    same order as ``dense_factors`` (Gaussian for Q1, Gaussian for Q2, k, m),
+    with the QR factorisations and the products K = Q1 diag(k) Q1^T,
+    M = Q2 diag(m) Q2^T done by torch on ``device`` (for large n, where the
+    host QR takes tens of seconds).  Returns (K, M, k, m) with K, M symmetric
+    FP64 device tensors and k, m NumPy vectors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    qs = []
+    for _ in range(2):
+        g = torch.from_numpy(rng.standard_normal((n, n))).to(device)
+        q, r = torch.linalg.qr(g)
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        qs.append(q * d[None, :])
+        del g, r
+    k = rng.uniform(lo, hi, n)
+    m = rng.uniform(lo, hi, n)
+    if n_zero_m:
+        m[:n_zero_m] = 0.0
+    out = []
+    for q, v in ((qs[0], k), (qs[1], m)):
+        a = (q * torch.from_numpy(v).to(device)[None, :]) @ q.T
+        out.append(0.5 * (a + a.T))
+    return out[0], out[1], k, m

@@ -80,7 +80,8 @@ typedef struct lrep_solve_opts {
     int32_t init_on_device;   /* init_U is a device pointer                             */
     int32_t result_on_device; /* lambda, X, Y are device pointers                       */
     int32_t precision;        /* 0: FP64 everywhere (default)                          */
-    int32_t reserved0;
+    int32_t profile;          /* 1: time every Step-6 operator apply with HIP events on
+                                 the solve's stream (results in lrep_stats_t.prof_*)  */
     double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this
                               (default 1e-12)                                          */
 } lrep_solve_opts_t;
@@ -100,6 +101,13 @@ typedef struct lrep_stats {
        small-scale problem (incl. projection and pull-back) / convergence check /
        P,Q / W,Z (incl. CG and MGS-Biorth)                                         */
     double  phase_ms[5];
+    /* with opts.profile: the block operator applies of the CG inner solves
+       (w columns each), timed kernel by kernel with HIP events               */
+    int64_t prof_launches;     /* timed apply-kernel launches                          */
+    double  prof_ms;           /* their summed GPU time                                */
+    double  prof_bytes;        /* algorithmic bytes they move (operator read once,
+                                  block read once, result written once)               */
+    double  prof_flops;        /* algorithmic flops (2 n^2 w dense)                     */
 } lrep_stats_t;
 
 /* Request for the serving interface (lrep_submit). */

@@ -64,7 +64,7 @@ class lrep_solve_opts_t(ctypes.Structure):
         ("init_on_device", ctypes.c_int32),
         ("result_on_device", ctypes.c_int32),
         ("precision", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("rebiorth_tol", ctypes.c_double),
     ]
 
@@ -81,6 +81,10 @@ class lrep_stats_t(ctypes.Structure):
         ("max_eps", ctypes.c_double),
         ("time_ms", ctypes.c_double),
         ("phase_ms", ctypes.c_double * 5),
+        ("prof_launches", ctypes.c_int64),
+        ("prof_ms", ctypes.c_double),
+        ("prof_bytes", ctypes.c_double),
+        ("prof_flops", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -244,7 +248,7 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0):
+              rebiorth_tol=0.0, profile=False):
     o = lrep_solve_opts_t()
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
@@ -252,6 +256,7 @@ def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=Non
         o.init_U, o.ld_init, o.init_on_device = p, ld, int(dev)
     o.result_on_device = int(result_on_device)
     o.rebiorth_tol = rebiorth_tol
+    o.profile = int(profile)
     return o
 
 

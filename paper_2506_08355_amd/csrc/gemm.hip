@@ -42,6 +42,14 @@ __device__ __forceinline__ const double* seg_col(const SegView& s, int c, int64_
     return s.p[i] + (int64_t)(c - s.start[i]) * s.ld[i];
 }
 
+// up to four independent products of the same shape in one launch
+constexpr int kMaxBatch = 4;
+struct NNBatch {
+    SegView A[kMaxBatch];
+    const double* B[kMaxBatch];
+    double* C[kMaxBatch];
+};
+
 SegView make_view(const Seg* segs, int nseg) {
     SegView v{};
     v.nseg = nseg;
@@ -66,11 +74,14 @@ SegView make_view(const Seg* segs, int nseg) {
 // --------------------------------------------------------------------------
 template <int BM, int BN, int WM>
 __global__ __launch_bounds__(NT) void gemm_nn_kernel(
-    int m, int q, int p, SegView A, const double* __restrict__ B, int64_t ldb,
-    double* __restrict__ C, int64_t ldc, double alpha, double beta,
+    int m, int q, int p, NNBatch bt, int ksplit, int64_t ldb, int64_t ldc, double alpha, double beta,
     int kchunk, double* __restrict__ part, const double* __restrict__ delta,
     const double* __restrict__ Yd, int64_t ldyd, const int* __restrict__ active_flag) {
     if (active_flag && *active_flag == 0) return;
+    const int bz = blockIdx.z / ksplit;
+    const SegView& A = bt.A[bz];
+    const double* __restrict__ B = bt.B[bz];
+    double* __restrict__ C = bt.C[bz];
     constexpr int WN = 4 / WM;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
@@ -81,7 +92,7 @@ __global__ __launch_bounds__(NT) void gemm_nn_kernel(
     const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
     const int wm = wid % WM, wn = wid / WM;
     const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
-    const int ks = blockIdx.z;
+    const int ks = blockIdx.z % ksplit;
     const int k_begin = ks * kchunk;
     const int k_end = min(p, k_begin + kchunk);
 
@@ -340,7 +351,7 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(
 hipError_t gemm_nn(hipStream_t st, int m, int q, int p, const Seg* A, int nsegA,
                    const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
                    double beta, double* work, size_t work_elems, const double* delta,
-                   const double* Yd, int64_t ldyd, int ksplit_hint, const int* active_flag) {
+                   const double* Yd, int64_t ldyd, int ksplit_hint, const int* active_flag, hipEvent_t* ev) {
     if (m <= 0 || q <= 0) return hipSuccess;
     SegView av = make_view(A, nsegA);
     int ksplit = 1;
@@ -374,19 +385,45 @@ hipError_t gemm_nn(hipStream_t st, int m, int q, int p, const Seg* A, int nsegA,
     }
     if (ksplit > 1) part = work;
     else kchunk = p;
+    NNBatch bt{};
+    bt.A[0] = av;
+    bt.B[0] = B;
+    bt.C[0] = C;
     dim3 grid(mt, nt, ksplit);
+    if (ev) (void)hipEventRecord(ev[0], st);
     if (wide)
-        hipLaunchKernelGGL((gemm_nn_kernel<64, 64, 2>), grid, dim3(NT), 0, st, m, q, p, av, B, ldb, C, ldc,
-                           alpha, beta, kchunk, part, delta, Yd, ldyd, active_flag);
+        hipLaunchKernelGGL((gemm_nn_kernel<64, 64, 2>), grid, dim3(NT), 0, st, m, q, p, bt, ksplit, ldb, ldc, alpha,
+                           beta, kchunk, part, delta, Yd, ldyd, active_flag);
     else
-        hipLaunchKernelGGL((gemm_nn_kernel<128, 32, 4>), grid, dim3(NT), 0, st, m, q, p, av, B, ldb, C, ldc,
-                           alpha, beta, kchunk, part, delta, Yd, ldyd, active_flag);
+        hipLaunchKernelGGL((gemm_nn_kernel<128, 32, 4>), grid, dim3(NT), 0, st, m, q, p, bt, ksplit, ldb, ldc, alpha,
+                           beta, kchunk, part, delta, Yd, ldyd, active_flag);
+    if (ev) (void)hipEventRecord(ev[1], st);
     if (part) {
         const int64_t tot = (int64_t)m * q;
         const int nb = (int)std::min<int64_t>(8192, (tot + NT - 1) / NT);
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nb), dim3(NT), 0, st, m, q, ksplit, part, C, ldc,
                            alpha, beta, delta, Yd, ldyd, active_flag);
     }
+    return hipGetLastError();
+}
+
+hipError_t gemm_nn_batch(hipStream_t st, int m, int q, int p, int nb, const Seg* A, const double* const* B,
+                         int64_t ldb, double* const* C, int64_t ldc, double alpha, double beta) {
+    if (m <= 0 || q <= 0 || nb <= 0) return hipSuccess;
+    if (nb > kMaxBatch || p <= 0) return hipErrorInvalidValue;
+    NNBatch bt{};
+    for (int i = 0; i < nb; ++i) {
+        bt.A[i] = make_view(&A[i], 1);
+        bt.B[i] = B[i];
+        bt.C[i] = C[i];
+    }
+    // narrow tiles and one k chunk: these products (p = subspace size) are latency bound,
+    // so the batch and the row tiles provide the parallelism
+    const int BM = 64, BN = 64;
+    dim3 grid((m + BM - 1) / BM, (q + BN - 1) / BN, nb);
+    hipLaunchKernelGGL((gemm_nn_kernel<64, 64, 2>), grid, dim3(NT), 0, st, m, q, p, bt, 1, ldb, ldc, alpha, beta, p,
+                       (double*)nullptr, (const double*)nullptr, (const double*)nullptr, (int64_t)0,
+                       (const int*)nullptr);
     return hipGetLastError();
 }
 

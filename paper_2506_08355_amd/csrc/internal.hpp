@@ -93,6 +93,7 @@ int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);
 
 // Operator apply with the roles (after a possible exchange): which = 0 -> "K", 1 -> "M".
 int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy,
-             double* work, size_t work_elems, double* small, const int* active_flag);
+             double* work, size_t work_elems, double* small, const int* active_flag,
+             hipEvent_t* ev = nullptr);
 
 }  // namespace lrep

@@ -22,6 +22,7 @@ enum StatusSlot : int {
     ST_NONFINITE = 1,    // NaN/Inf seen
     ST_NKEPT = 2,        // columns kept by the last coefficient MGS
     ST_NP = 3,           // columns of P^ kept by Step 5
+    ST_SWEEPS = 4,       // Jacobi sweeps of the last small LREP
     ST_COUNT = 8
 };
 
@@ -32,12 +33,28 @@ hipError_t gemm_nn(hipStream_t st, int m, int q, int p, const Seg* A, int nsegA,
                    const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
                    double beta, double* work, size_t work_elems,
                    const double* delta = nullptr, const double* Yd = nullptr,
-                   int64_t ldyd = 0, int ksplit_hint = 0, const int* active_flag = nullptr);
+                   int64_t ldyd = 0, int ksplit_hint = 0, const int* active_flag = nullptr,
+                   hipEvent_t* ev = nullptr);   // ev[0], ev[1] recorded around the product kernel
+
+// nb (<= 4) independent products C_i = alpha A_i B_i + beta C_i of one shape
+// (A_i single segments) in a single launch.
+hipError_t gemm_nn_batch(hipStream_t st, int m, int q, int p, int nb, const Seg* A,
+                         const double* const* B, int64_t ldb, double* const* C, int64_t ldc,
+                         double alpha, double beta);
 
 hipError_t gemm_tn(hipStream_t st, int n, int p, int q, const Seg* A, int nsegA,
                    const Seg* B, int nsegB, double* C, int64_t ldc, double alpha,
                    int symmetrize, double* work, size_t work_elems,
                    const int* active_flag = nullptr);
+
+// ---- apply.hip -----------------------------------------------------------
+// C = alpha * A X + beta * C for a dense A (m x p, lda even, 16-byte aligned)
+// and a narrow X (p x q, q <= 32): the streaming block apply of the CG inner
+// solves.  `ev` (optional) brackets the main product kernel.
+hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double* A, int64_t lda,
+                              const double* X, int64_t ldx, double* C, int64_t ldc, double alpha,
+                              double beta, double* work, size_t work_elems,
+                              const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
 
 // ---- vec.hip -------------------------------------------------------------
 // Y[:, j] = delta o X[:, j]
@@ -102,27 +119,30 @@ hipError_t combine_ab(hipStream_t st, int64_t n, double* K, double* M);
 // zero a column block
 hipError_t zero_cols(hipStream_t st, int n, int cols, double* X, int64_t ld);
 
-// ---- small.hip (one workgroup kernels on d x d data) ----------------------
-// Small structured LREP:  K^ = L1 L1^T, M^ = L2 L2^T, SVD of L1^T L2 by
+// ---- small.hip (small d x d data, d <= 128) ------------------------------
+// Small structured LREP:  K^ = L1 L1^T, M^ = L2 L2^T, SVD of L2^T L1 by
 // one-sided Jacobi, all d Ritz pairs ascending: lam[d], Xh (d x d, ld kMaxD),
-// Yh.  `scratch` >= 3 * kMaxD * kMaxD doubles.  status[ST_NOTSPD] set on
-// Cholesky failure.
+// Yh.  `scratch` >= 4 * kMaxD^2 doubles; `work` is the block-product
+// workspace.  status[ST_NOTSPD] set on Cholesky failure.
 hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh, int64_t ldh,
-                      double* lam, double* Xh, double* Yh, double* scratch, int* status);
+                      double* lam, double* Xh, double* Yh, double* scratch, int* status,
+                      double* work, size_t work_elems);
 
 // Step 5 in coefficient space: for window Ritz indices win[0..nw):
 //   P^ = (I - Xk Yk^T)^2 (Xh[:, g] - e_g), Q^ likewise, Xk = Xh[:, 0:hi];
 // columns the projector annihilates are dropped, then MGS-Biorth (drop rule
 // of the oracle).  Writes P^, Q^ (d x np, ld kMaxD) and status[ST_NP] = np.
+// `scratch` >= 3 * kMaxD * 64 + 128 doubles.
 hipError_t step5_pq(hipStream_t st, int d, int hi, const double* Xh, const double* Yh,
                     const int* win, int nw, double* Ph, double* Qh, double* scratch,
-                    int* status, double cos_tol, double dep_tol);
+                    int* status, double cos_tol, double dep_tol, double* work, size_t work_elems);
 
 // Coefficient pass of block MGS-Biorth.  G is the Gram of [X Y] (2m x 2m,
 // ld ldg).  Runs the MGS-Biorth recurrence (Algorithm MGS-Biorth) on the
-// coefficient vectors: P = X A, Q = Y B with A, B upper triangular (m x m,
-// ld kMaxD; dropped columns compacted away).  status[ST_NKEPT] = kept count.
+// coefficient vectors: P = X A, Q = Y B with A, B upper triangular (m x np,
+// ld kMaxD; dropped columns compacted away).  status[ST_NKEPT] = np.
+// `scratch` >= 2 * kMaxD^2 doubles.
 hipError_t coef_mgs(hipStream_t st, int m, const double* G, int64_t ldg, double* A, double* B,
-                    int* status, double cos_tol, double dep_tol);
+                    int* status, double cos_tol, double dep_tol, double* scratch);
 
 }  // namespace lrep

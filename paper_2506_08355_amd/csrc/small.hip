@@ -11,11 +11,18 @@
 //              [psi_c sigma_c; L1 phi_c], so
 //                  Y^_c = L1 phi_c / sqrt(sigma_c),
 //                  X^_c = L2 psi_c / sqrt(sigma_c) = L2 (B phi_c) / sigma_c^(3/2).
-//  step5_pq    Step 5 in coefficient space (equation for P^, Q^) with the
-//              small MGS-Biorth.
+//              The dense products B = L2^T L1 and X^ = L2 T run as MFMA
+//              block products (gemm.hip); the Cholesky factorisations and
+//              the Jacobi sweeps are one-workgroup kernels.
+//  step5_pq    Step 5 in coefficient space (equation for P^, Q^): the two
+//              projector applications are block products, followed by the
+//              small MGS-Biorth on explicit d-vectors.
 //  coef_mgs    the coefficient pass of block MGS-Biorth: the recurrence of
 //              Algorithm MGS-Biorth run on coefficient vectors with every
 //              inner product taken from the Gram matrix of [X Y].
+// The MGS-Biorth recurrences run right-looking (after p_l, q_l are final,
+// every later column is updated against them); each pair (l, j) sees the
+// same coefficients, in the same order, as in the column-by-column form.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -23,136 +30,194 @@ namespace lrep {
 
 namespace {
 
-constexpr double JACOBI_TOL = 1e-15;
+// convergence: every pair's cosine below ~ sqrt(d) eps (the usual one-sided
+// Jacobi criterion)
+constexpr double JACOBI_TOL = 4e-15;
 constexpr int JACOBI_MAX_SWEEPS = 40;
+constexpr int LD = kMaxD + 1;
+constexpr size_t D2 = (size_t)kMaxD * kMaxD;
 
-// Cholesky of the symmetric part of A (d x d, lda) into L (lower, ld kMaxD,
-// strict upper part zeroed).  LDS matrix `S` has room for kMaxD x (kMaxD+1).
-// Returns false (uniformly) if a pivot is not positive.
-__device__ bool chol_lds(int d, const double* __restrict__ A, int64_t lda, double* __restrict__ L,
-                         double* S, int* flag) {
+// ---- cross-lane sums with DPP (row-local) and readlane (across rows) ------
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
+    p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_readlane(p.x, l);
+    p.y = __builtin_amdgcn_readlane(p.y, l);
+    return __builtin_bit_cast(double, p);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_rows(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, ROWMASK, 0xF, false);
+    p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, ROWMASK, 0xF, false);
+    return __builtin_bit_cast(double, p);
+}
+// Sum over the 64 lanes.  Within each row of 16 lanes: xor-1 and xor-2 quad
+// permutes, then half-mirror and mirror (each stage adds two equal partial
+// sums in either order, so all 16 lanes hold bitwise the same row sum); then
+// row 1 += row 0 and row 3 += row 2 (row_bcast:15), row 3 += row 1
+// (row_bcast:31), and lane 63's total is broadcast from a scalar register.
+// Every lane returns bitwise the same total.
+__device__ __forceinline__ double wsum(double v) {
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    v += dpp_rows<0x142, 0xA>(v);
+    v += dpp_rows<0x143, 0xC>(v);
+    return readlane(v, 63);
+}
+
+// stacked row e * 64 + lane lies in the top (B) part: rows < D = 32 E
+template <int E>
+__device__ __forceinline__ bool is_top(int e, int lane) {
+    if constexpr (E >= 2) return e < E / 2;
+    else return lane < 32;
+}
+
+// 1 / x to full precision from the hardware estimate and one Newton step
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+// 1 / sqrt(x) from the hardware estimate and one Newton step
+__device__ __forceinline__ double rsq_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x * r;
+    return fma(r, fma(-h, r, 0.5), r);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of the symmetric parts of K^ (block 0) and M^ (block 1), d <= 128.
+// Right-looking on an LDS copy; one barrier per column: at step k every
+// thread reads the final pivot S[k][k] and column k (unscaled), writes the
+// scaled column of L to global memory and updates its own trailing entries
+// with S[i][j] -= S[i][k] S[j][k] / S[k][k].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void chol2_kernel(int d, const double* __restrict__ Kh,
+                                                    const double* __restrict__ Mh, int64_t ldh,
+                                                    double* __restrict__ scratch, int* __restrict__ status) {
+    __shared__ double S[kMaxD * LD];
+    const double* A = blockIdx.x == 0 ? Kh : Mh;
+    double* L = scratch + (size_t)blockIdx.x * D2;
     const int tid = threadIdx.x, nt = blockDim.x;
-    constexpr int LD = kMaxD + 1;
     for (int idx = tid; idx < d * d; idx += nt) {
         const int i = idx % d, j = idx / d;
-        S[i * LD + j] = 0.5 * (A[(int64_t)j * lda + i] + A[(int64_t)i * lda + j]);
+        S[i * LD + j] = 0.5 * (A[(int64_t)j * ldh + i] + A[(int64_t)i * ldh + j]);
     }
-    if (tid == 0) *flag = 0;
+    for (int idx = tid; idx < (int)D2; idx += nt) L[idx] = 0.0;
     __syncthreads();
     for (int k = 0; k < d; ++k) {
-        if (tid == 0) {
-            const double v = S[k * LD + k];
-            if (!(v > 0.0)) *flag = 1;
-            else S[k * LD + k] = sqrt(v);
+        const double v = S[k * LD + k];
+        if (!(v > 0.0)) {
+            if (tid == 0) status[ST_NOTSPD] = 1;
+            return;   // uniform: every thread read the same pivot
         }
-        __syncthreads();
-        if (*flag) return false;
-        const double piv = S[k * LD + k];
-        for (int i = k + 1 + tid; i < d; i += nt) S[i * LD + k] /= piv;
-        __syncthreads();
+        const double piv = sqrt(v);
+        const double inv = 1.0 / v;
+        for (int i = k + tid; i < d; i += nt) L[(int64_t)k * kMaxD + i] = (i == k) ? piv : S[i * LD + k] / piv;
         const int m = d - k - 1;
         for (int idx = tid; idx < m * m; idx += nt) {
             const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-            if (j <= i) S[i * LD + j] -= S[i * LD + k] * S[j * LD + k];
+            if (j <= i) S[i * LD + j] -= S[i * LD + k] * S[j * LD + k] * inv;
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < kMaxD * kMaxD; idx += nt) {
-        const int i = idx % kMaxD, j = idx / kMaxD;
-        L[(int64_t)j * kMaxD + i] = (i < d && j < d && j <= i) ? S[i * LD + j] : 0.0;
-    }
-    __syncthreads();
-    return true;
 }
 
+// ---------------------------------------------------------------------------
+// One-sided Jacobi on the stacked columns [B; L1] (B = L2^T L1, both d x d,
+// ld kMaxD), round-robin ordering.  Wavefront w owns tournament slots
+// T[4w..4w+3] (register slots 0..3) and Bt[4w..4w+3] (slots 4..7); lane l
+// holds stacked rows e*64 + l.  Outputs lam (ascending), Yh = L1 phi /
+// sqrt(sigma) and T = (B phi) / sigma^(3/2) (so that X^ = L2 T).
+// ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(D * 8) void small_lrep_kernel(int d, const double* __restrict__ Kh,
-                                                          const double* __restrict__ Mh, int64_t ldh,
-                                                          double* __restrict__ lam, double* __restrict__ Xh,
-                                                          double* __restrict__ Yh, double* __restrict__ scratch,
-                                                          int* __restrict__ status) {
-    constexpr int NW = D / 8;            // wavefronts
+__global__ __launch_bounds__(D * 8) void jacobi_kernel(int d, const double* __restrict__ scratch,
+                                                      double* __restrict__ lam, double* __restrict__ Yh,
+                                                      double* __restrict__ T, int* __restrict__ status) {
+    constexpr int NW = D / 8;
     constexpr int NTH = NW * WAVE;
-    constexpr int E = (2 * D) / WAVE;    // stacked elements per lane per column
-    constexpr int M = D / 2;             // pairs
-    constexpr size_t CHOL = (size_t)kMaxD * (kMaxD + 1);
-    constexpr size_t XCH = (size_t)2 * 2 * NW * 2 * D;
-    constexpr size_t LDSN = CHOL > XCH ? CHOL : XCH;
-    __shared__ double lds[LDSN];
+    constexpr int E = (2 * D) / WAVE;
+    __shared__ double xT[2 * NW * (2 * D + 2)];
+    __shared__ double xB[2 * NW * (2 * D + 2)];
     __shared__ double sig[D];
     __shared__ double bnorm[D];
     __shared__ int rank_of[D];
-    __shared__ int flag;
     __shared__ double wmax[NW];
-
+    const double* L1 = scratch;
+    const double* Bm = scratch + 3 * D2;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-    double* L1 = scratch;
-    double* L2 = scratch + kMaxD * kMaxD;
-    double* T = scratch + 2 * kMaxD * kMaxD;
 
-    if (!chol_lds(d, Kh, ldh, L1, lds, &flag) || !chol_lds(d, Mh, ldh, L2, lds, &flag)) {
-        if (tid == 0) status[ST_NOTSPD] = 1;
-        return;
-    }
-
-    // ---- load stacked columns [B; L1], B = L2^T L1 (upper-times-lower) -------
-    // slots 0..3 = T[4w..4w+3] (tournament "top" row), 4..7 = Bt[4w..4w+3]
     double col[8][E];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const int k = 4 * w + (s & 3);
-        const int c = (s < 4) ? 2 * k : 2 * k + 1;   // initial column in this slot
+        const int c = (s < 4) ? 2 * k : 2 * k + 1;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int row = e * WAVE + lane;
             double v = 0.0;
             if (c < d) {
                 if (row < D) {
-                    if (row < d) {
-                        // B[row][c] = sum_k L2[k][row] L1[k][c], k >= max(row, c)
-                        const int k0 = row > c ? row : c;
-                        for (int kk = k0; kk < d; ++kk)
-                            v += L2[(int64_t)row * kMaxD + kk] * L1[(int64_t)c * kMaxD + kk];
-                    }
-                } else {
-                    const int r = row - D;
-                    if (r < d) v = L1[(int64_t)c * kMaxD + r];
+                    if (row < d) v = Bm[(int64_t)c * kMaxD + row];
+                } else if (row - D < d) {
+                    v = L1[(int64_t)c * kMaxD + (row - D)];
                 }
             }
             col[s][e] = v;
         }
     }
-    __syncthreads();   // LDS (Cholesky) is reused below
 
-    double* xT = lds;                       // [2][NW][2D]
-    double* xB = lds + 2 * NW * 2 * D;      // [2][NW][2D]
-
+    // squared norms of the top parts travel with their columns (uniform per
+    // wave); they are recomputed exactly at the start of every sweep and
+    // updated by the rotation formulas in between (alpha' = alpha - t gamma,
+    // beta' = beta + t gamma), so each pair needs one cross-lane sum only.
+    double nrm[8];
+    int sweeps = 0;
     for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+        ++sweeps;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (is_top<E>(e, lane)) t += col[s][e] * col[s][e];
+            nrm[s] = wsum(t);
+        }
         double offmax = 0.0;
         for (int step = 0; step < D - 1; ++step) {
-            // rotate the four pairs (slot i, slot 4+i)
+            double ga[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                double al = 0, be = 0, ga = 0;
+                ga[i] = 0.0;
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    if (e * WAVE + lane < D) {
-                        const double a = col[i][e], b = col[4 + i][e];
-                        al += a * a;
-                        be += b * b;
-                        ga += a * b;
-                    }
-                }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (ga != 0.0) {
-                    const double rel = fabs(ga) / sqrt(al * be);
+                for (int e = 0; e < E; ++e)
+                    if (is_top<E>(e, lane)) ga[i] += col[i][e] * col[4 + i][e];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ga[i] = wsum(ga[i]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double al = nrm[i], be = nrm[4 + i];
+                if (ga[i] != 0.0) {
+                    const double rel = fabs(ga[i]) * rsq_nr(al * be);
                     offmax = fmax(offmax, rel);
                     if (rel > JACOBI_TOL) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + t * t);
+                        // Rutishauser's rotation: zeta = (beta - alpha) / (2 gamma),
+                        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t
+                        const double zeta = (be - al) * rcp_nr(2.0 * ga[i]);
+                        const double az = fabs(zeta);
+                        const double root = az < 1e150 ? (1.0 + zeta * zeta) * rsq_nr(1.0 + zeta * zeta) : az;
+                        const double t = copysign(rcp_nr(az + root), zeta);
+                        const double c = rsq_nr(1.0 + t * t);
                         const double s = c * t;
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
@@ -160,27 +225,40 @@ __global__ __launch_bounds__(D * 8) void small_lrep_kernel(int d, const double* 
                             col[i][e] = c * a - s * b;
                             col[4 + i][e] = s * a + c * b;
                         }
+                        nrm[i] = al - t * ga[i];
+                        nrm[4 + i] = be + t * ga[i];
+                        if (nrm[i] < 1e-2 * al) {   // heavy cancellation: recompute exactly
+                            double t2 = 0.0;
+#pragma unroll
+                            for (int e = 0; e < E; ++e)
+                                if (is_top<E>(e, lane)) t2 += col[i][e] * col[i][e];
+                            nrm[i] = wsum(t2);
+                        }
                     }
                 }
             }
-            // round-robin move; only boundary columns cross wavefronts
+            // round-robin move: only T[4w+3] and Bt[4w] cross wavefronts
             const int par = step & 1;
-            double* oT = xT + ((size_t)par * NW + w) * 2 * D;
-            double* oB = xB + ((size_t)par * NW + w) * 2 * D;
+            double* oT = xT + ((size_t)par * NW + w) * (2 * D + 2);
+            double* oB = xB + ((size_t)par * NW + w) * (2 * D + 2);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                oT[e * WAVE + lane] = col[3][e];   // T[4w+3] -> wave w+1
-                oB[e * WAVE + lane] = col[4][e];   // Bt[4w]  -> wave w-1
+                oT[e * WAVE + lane] = col[3][e];
+                oB[e * WAVE + lane] = col[4][e];
+            }
+            if (lane == 0) {
+                oT[2 * D] = nrm[3];
+                oB[2 * D] = nrm[4];
             }
             __syncthreads();
-            const double* iT = xT + ((size_t)par * NW + (w > 0 ? w - 1 : 0)) * 2 * D;
-            const double* iB = xB + ((size_t)par * NW + (w < NW - 1 ? w + 1 : 0)) * 2 * D;
+            const double* iT = xT + ((size_t)par * NW + (w > 0 ? w - 1 : 0)) * (2 * D + 2);
+            const double* iB = xB + ((size_t)par * NW + (w < NW - 1 ? w + 1 : 0)) * (2 * D + 2);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double t0 = col[0][e], t1 = col[1][e], t2 = col[2][e], t3 = col[3][e];
                 const double b0 = col[4][e], b1 = col[5][e], b2 = col[6][e], b3 = col[7][e];
                 if (w == 0) {
-                    col[0][e] = t0;        // fixed
+                    col[0][e] = t0;
                     col[1][e] = b0;
                 } else {
                     col[0][e] = iT[e * WAVE + lane];
@@ -193,8 +271,23 @@ __global__ __launch_bounds__(D * 8) void small_lrep_kernel(int d, const double* 
                 col[6][e] = b3;
                 col[7][e] = (w == NW - 1) ? t3 : iB[e * WAVE + lane];
             }
+            {
+                const double t0 = nrm[0], t1 = nrm[1], t2 = nrm[2], t3 = nrm[3];
+                const double b0 = nrm[4], b1 = nrm[5], b2 = nrm[6], b3 = nrm[7];
+                if (w == 0) {
+                    nrm[1] = b0;
+                } else {
+                    nrm[0] = iT[2 * D];
+                    nrm[1] = t0;
+                }
+                nrm[2] = t1;
+                nrm[3] = t2;
+                nrm[4] = b1;
+                nrm[5] = b2;
+                nrm[6] = b3;
+                nrm[7] = (w == NW - 1) ? t3 : iB[2 * D];
+            }
         }
-        // sweep convergence (uniform decision)
         if (lane == 0) wmax[w] = offmax;
         __syncthreads();
         double om = 0.0;
@@ -203,27 +296,25 @@ __global__ __launch_bounds__(D * 8) void small_lrep_kernel(int d, const double* 
         __syncthreads();
         if (om <= JACOBI_TOL) break;
     }
+    if (tid == 0 && status) status[ST_SWEEPS] = sweeps;
 
-    // ---- singular values, ordering, outputs --------------------------------
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         double tn = 0, bn = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const double v = col[s][e];
-            if (e * WAVE + lane < D) tn += v * v;
+            if (is_top<E>(e, lane)) tn += v * v;
             else bn += v * v;
         }
-        tn = wave_sum(tn);
-        bn = wave_sum(bn);
-        const int slot = 8 * w + s;
+        tn = wsum(tn);
+        bn = wsum(bn);
         if (lane == 0) {
-            sig[slot] = sqrt(tn);
-            bnorm[slot] = bn;
+            sig[8 * w + s] = sqrt(tn);
+            bnorm[8 * w + s] = bn;
         }
     }
     __syncthreads();
-    // rank among live (non-padding) columns: ascending sigma, ties by slot
     for (int a = tid; a < D; a += NTH) {
         int r = -1;
         if (bnorm[a] > 0.0) {
@@ -253,242 +344,283 @@ __global__ __launch_bounds__(D * 8) void small_lrep_kernel(int d, const double* 
         }
         if (lane == 0) lam[r] = sg;
     }
-    __syncthreads();
-    __threadfence_block();
-    // X^ = L2 T (L2 lower triangular)
-    for (int idx = tid; idx < d * d; idx += NTH) {
-        const int i = idx % d, c = idx / d;
-        double v = 0.0;
-        for (int k = 0; k <= i; ++k) v += L2[(int64_t)k * kMaxD + i] * T[(int64_t)c * kMaxD + k];
-        Xh[(int64_t)c * kMaxD + i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Step 5, gather:  V = Xh[:, win] - E, U = Yh[:, win] - E (d x nw, ld kMaxD)
+// and their column norms (for the "annihilated by the projector" test).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void step5_gather_kernel(int d, const double* __restrict__ Xh,
+                                                           const double* __restrict__ Yh, const int* __restrict__ win,
+                                                           int nw, double* __restrict__ V, double* __restrict__ U,
+                                                           double* __restrict__ n0) {
+    __shared__ double red[256 / WAVE];
+    const int j = blockIdx.x;
+    const int g = win[j];
+    double sv = 0, su = 0;
+    for (int i = threadIdx.x; i < d; i += 256) {
+        const double e = (i == g) ? 1.0 : 0.0;
+        const double v = Xh[(int64_t)g * kMaxD + i] - e;
+        const double u = Yh[(int64_t)g * kMaxD + i] - e;
+        V[(int64_t)j * kMaxD + i] = v;
+        U[(int64_t)j * kMaxD + i] = u;
+        sv += v * v;
+        su += u * u;
+    }
+    sv = block_sum<256>(sv, red);
+    su = block_sum<256>(su, red);
+    if (threadIdx.x == 0) {
+        n0[j] = sqrt(sv);
+        n0[64 + j] = sqrt(su);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step 5.  256 threads.  V, U columns (d x nw) live in LDS.
+// MGS-Biorth of explicit small vectors (d x nw, ld kMaxD, in place in LDS),
+// right-looking, with the oracle's breakdown rule; columns whose norm the
+// projector reduced below dep_tol * n0 are skipped first.  Writes the kept
+// columns compacted to Ph, Qh and status[ST_NP].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void step5_kernel(int d, int hi, const double* __restrict__ Xh,
-                                                    const double* __restrict__ Yh, const int* __restrict__ win,
-                                                    int nw, double* __restrict__ Ph, double* __restrict__ Qh,
-                                                    double* __restrict__ C, int* __restrict__ status,
-                                                    double cos_tol, double dep_tol) {
-    __shared__ double V[kMaxD * 64];
-    __shared__ double U[kMaxD * 64];
-    __shared__ double n0v[64], n0u[64];
+__global__ __launch_bounds__(256) void small_mgs_kernel(int d, int nw, const double* __restrict__ Vin,
+                                                        const double* __restrict__ Uin,
+                                                        const double* __restrict__ n0, double* __restrict__ Ph,
+                                                        double* __restrict__ Qh, int* __restrict__ status,
+                                                        double cos_tol, double dep_tol) {
+    __shared__ double P[kMaxD * 64];
+    __shared__ double Q[kMaxD * 64];
+    __shared__ double xn[64], yn[64], rr[64], ss[64];
     __shared__ int live[64];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double red[256 / WAVE];
+    __shared__ double sc[4];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid % WAVE, wid = tid / WAVE;
     for (int idx = tid; idx < d * nw; idx += nt) {
         const int i = idx % d, j = idx / d;
-        const int g = win[j];
-        const double e = (i == g) ? 1.0 : 0.0;
-        V[j * kMaxD + i] = Xh[(int64_t)g * kMaxD + i] - e;
-        U[j * kMaxD + i] = Yh[(int64_t)g * kMaxD + i] - e;
+        P[j * kMaxD + i] = Vin[(int64_t)j * kMaxD + i];
+        Q[j * kMaxD + i] = Uin[(int64_t)j * kMaxD + i];
     }
     __syncthreads();
-    for (int j = tid; j < nw; j += nt) {
+    // column norms of the projected inputs (x_l, y_l of the MGS) and liveness
+    for (int j = wid; j < nw; j += nt / WAVE) {
         double a = 0, b = 0;
-        for (int i = 0; i < d; ++i) {
-            a += V[j * kMaxD + i] * V[j * kMaxD + i];
-            b += U[j * kMaxD + i] * U[j * kMaxD + i];
+        for (int i = lane; i < d; i += WAVE) {
+            a += P[j * kMaxD + i] * P[j * kMaxD + i];
+            b += Q[j * kMaxD + i] * Q[j * kMaxD + i];
         }
-        n0v[j] = sqrt(a);
-        n0u[j] = sqrt(b);
+        a = sqrt(wsum(a));
+        b = sqrt(wsum(b));
+        if (lane == 0) {
+            xn[j] = a;
+            yn[j] = b;
+            live[j] = (a > dep_tol * n0[j]) && (b > dep_tol * n0[64 + j]);
+        }
     }
     __syncthreads();
-    // two applications of each projector; C (global scratch) holds hi x nw coefficients
-    for (int side = 0; side < 2; ++side) {
-        double* Vs = side == 0 ? V : U;
-        const double* Pb = side == 0 ? Xh : Yh;   // basis
-        const double* Pd = side == 0 ? Yh : Xh;   // dual
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int idx = tid; idx < hi * nw; idx += nt) {
-                const int i = idx % hi, j = idx / hi;
-                double s = 0;
-                for (int k = 0; k < d; ++k) s += Pd[(int64_t)i * kMaxD + k] * Vs[j * kMaxD + k];
-                C[(int64_t)j * kMaxD + i] = s;
-            }
-            __syncthreads();
-            __threadfence_block();
-            for (int idx = tid; idx < d * nw; idx += nt) {
-                const int k = idx % d, j = idx / d;
-                double s = 0;
-                for (int i = 0; i < hi; ++i) s += Pb[(int64_t)i * kMaxD + k] * C[(int64_t)j * kMaxD + i];
-                Vs[j * kMaxD + k] -= s;
-            }
-            __syncthreads();
+    int np = 0;
+    for (int l = 0; l < nw; ++l) {
+        if (!live[l]) continue;
+        const double* p = P + l * kMaxD;
+        const double* q = Q + l * kMaxD;
+        double eta = 0, pn = 0, qn = 0;
+        for (int i = tid; i < d; i += nt) {
+            eta += p[i] * q[i];
+            pn += p[i] * p[i];
+            qn += q[i] * q[i];
         }
-    }
-    for (int j = tid; j < nw; j += nt) {
-        double a = 0, b = 0;
-        for (int i = 0; i < d; ++i) {
-            a += V[j * kMaxD + i] * V[j * kMaxD + i];
-            b += U[j * kMaxD + i] * U[j * kMaxD + i];
+        eta = block_sum<256>(eta, red);
+        pn = sqrt(block_sum<256>(pn, red));
+        qn = sqrt(block_sum<256>(qn, red));
+        if (eta == 0.0 || fabs(eta) <= cos_tol * pn * qn || pn <= dep_tol * xn[l] || qn <= dep_tol * yn[l]) continue;
+        const double sl = sqrt(fabs(eta));
+        const double rl = eta < 0 ? -sl : sl;
+        for (int i = tid; i < d; i += nt) {
+            const double pv = p[i] / rl, qv = q[i] / sl;
+            P[l * kMaxD + i] = pv;
+            Q[l * kMaxD + i] = qv;
+            Ph[(int64_t)np * kMaxD + i] = pv;
+            Qh[(int64_t)np * kMaxD + i] = qv;
         }
-        live[j] = (sqrt(a) > dep_tol * n0v[j]) && (sqrt(b) > dep_tol * n0u[j]);
-    }
-    __syncthreads();
-    // MGS-Biorth on live columns, one wavefront (lanes over rows)
-    if (tid < WAVE) {
-        const int lane = tid;
-        int np = 0;
-        for (int l = 0; l < nw; ++l) {
-            if (!live[l]) continue;
-            double* p = V + l * kMaxD;
-            double* q = U + l * kMaxD;
-            double xn = 0, yn = 0;
+        ++np;
+        __syncthreads();
+        // coefficients for every later column: r_j = q_l . p_j, s_j = p_l . q_j
+        for (int j = l + 1 + wid; j < nw; j += nt / WAVE) {
+            double r = 0, s = 0;
             for (int i = lane; i < d; i += WAVE) {
-                xn += p[i] * p[i];
-                yn += q[i] * q[i];
+                r += q[i] * P[j * kMaxD + i];
+                s += p[i] * Q[j * kMaxD + i];
             }
-            xn = sqrt(wave_sum(xn));
-            yn = sqrt(wave_sum(yn));
-            for (int j = 0; j < np; ++j) {
-                const double* pj = Ph + (int64_t)j * kMaxD;
-                const double* qj = Qh + (int64_t)j * kMaxD;
-                double r = 0;
-                for (int i = lane; i < d; i += WAVE) r += qj[i] * p[i];
-                r = wave_sum(r);
-                for (int i = lane; i < d; i += WAVE) p[i] -= r * pj[i];
-                double s = 0;
-                for (int i = lane; i < d; i += WAVE) s += pj[i] * q[i];
-                s = wave_sum(s);
-                for (int i = lane; i < d; i += WAVE) q[i] -= s * qj[i];
+            r = wsum(r);
+            s = wsum(s);
+            if (lane == 0) {
+                rr[j] = r;
+                ss[j] = s;
             }
-            double eta = 0, pn = 0, qn = 0;
-            for (int i = lane; i < d; i += WAVE) {
-                eta += p[i] * q[i];
-                pn += p[i] * p[i];
-                qn += q[i] * q[i];
-            }
-            eta = wave_sum(eta);
-            pn = sqrt(wave_sum(pn));
-            qn = sqrt(wave_sum(qn));
-            if (eta == 0.0 || fabs(eta) <= cos_tol * pn * qn || pn <= dep_tol * xn || qn <= dep_tol * yn) continue;
-            const double sl = sqrt(fabs(eta));
-            const double rl = eta < 0 ? -sl : sl;
-            for (int i = lane; i < d; i += WAVE) {
-                Ph[(int64_t)np * kMaxD + i] = p[i] / rl;
-                Qh[(int64_t)np * kMaxD + i] = q[i] / sl;
-            }
-            ++np;
         }
-        if (lane == 0) status[ST_NP] = np;
+        __syncthreads();
+        for (int idx = tid; idx < d * (nw - l - 1); idx += nt) {
+            const int i = idx % d, j = l + 1 + idx / d;
+            P[j * kMaxD + i] -= rr[j] * p[i];
+            Q[j * kMaxD + i] -= ss[j] * q[i];
+        }
+        __syncthreads();
     }
+    if (tid == 0) status[ST_NP] = np;
+    (void)sc;
 }
 
 // ---------------------------------------------------------------------------
-// coefficient pass of block MGS-Biorth.  One wavefront does the recurrence;
-// lanes run over the m coefficients.
+// Coefficient pass of block MGS-Biorth (right-looking).  G = [[Gxx, Gxy],
+// [Gyx, Gyy]] is the Gram of [X Y] (2m x 2m, ld ldg).  a_j, b_j (columns of
+// A, B, m x m in global scratch, ld kMaxD) are the coefficients of the
+// current p~_j = X a_j, q~_j = Y b_j.  Per step l:
+//   eta = a_l^T Gxy b_l, |p~_l|^2 = a_l^T Gxx a_l, |q~_l|^2 = b_l^T Gyy b_l;
+//   scale, then for j > l: r_j = (Gxy b_l) . a_j, a_j -= r_j a_l;
+//                          s_j = (Gxy^T a_l) . b_j, b_j -= s_j b_l.
+// Kept columns are copied compacted to Aout, Bout.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void coef_mgs_kernel(int m, const double* __restrict__ G, int64_t ldg,
-                                                      double* __restrict__ A, double* __restrict__ B,
-                                                      int* __restrict__ status, double cos_tol, double dep_tol) {
-    // G = [[Gxx, Gxy], [Gyx, Gyy]] of [X Y];  a_l, b_l: coefficients of p_l, q_l
-    __shared__ double a[kMaxD], b[kMaxD];
-    __shared__ double hq[kMaxD * kMaxD];   // row j: b_j^T Gyx  (so q_j . X c = hq_j . c)
-    // hp_j = a_j^T Gxy is stored in the output slot region of A's spare space;
-    // kept in global scratch B + kMaxD*kMaxD (caller provides 2 kMaxD^2 doubles for B)
-    double* hp = B + (int64_t)kMaxD * kMaxD;
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void coef_mgs_kernel(int m, const double* __restrict__ G, int64_t ldg,
+                                                       double* __restrict__ A, double* __restrict__ B,
+                                                       double* __restrict__ Aout, double* __restrict__ Bout,
+                                                       int* __restrict__ status, double cos_tol, double dep_tol) {
+    __shared__ double txy[kMaxD], txx[kMaxD], tyy[kMaxD], u[kMaxD], rr[kMaxD], ss[kMaxD];
+    __shared__ double red[256 / WAVE];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid % WAVE, wid = tid / WAVE;
     auto gxx = [&](int i, int j) { return G[(int64_t)j * ldg + i]; };
     auto gxy = [&](int i, int j) { return G[(int64_t)(m + j) * ldg + i]; };
     auto gyy = [&](int i, int j) { return G[(int64_t)(m + j) * ldg + (m + i)]; };
+    for (int idx = tid; idx < m * m; idx += nt) {
+        const int i = idx % m, j = idx / m;
+        A[(int64_t)j * kMaxD + i] = (i == j) ? 1.0 : 0.0;
+        B[(int64_t)j * kMaxD + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
     int np = 0;
     for (int l = 0; l < m; ++l) {
-        for (int i = lane; i < m; i += WAVE) {
-            a[i] = (i == l) ? 1.0 : 0.0;
-            b[i] = a[i];
+        const double* al = A + (int64_t)l * kMaxD;
+        const double* bl = B + (int64_t)l * kMaxD;
+        // a_l, b_l are supported on rows 0..l
+        for (int t = tid; t < 4 * m; t += nt) {
+            const int which = t / m, i = t % m;
+            double s = 0;
+            if (which == 0)
+                for (int k = 0; k <= l; ++k) s += gxy(i, k) * bl[k];
+            else if (which == 1)
+                for (int k = 0; k <= l; ++k) s += gxx(i, k) * al[k];
+            else if (which == 2)
+                for (int k = 0; k <= l; ++k) s += gyy(i, k) * bl[k];
+            else
+                for (int k = 0; k <= l; ++k) s += gxy(k, i) * al[k];
+            (which == 0 ? txy : which == 1 ? txx : which == 2 ? tyy : u)[i] = s;
         }
         __syncthreads();
-        for (int j = 0; j < np; ++j) {
-            // r = q_j . p  = hq_j . a
-            double r = 0;
-            for (int i = lane; i < m; i += WAVE) r += hq[j * kMaxD + i] * a[i];
-            r = wave_sum(r);
-            for (int i = lane; i < m; i += WAVE) a[i] -= r * A[(int64_t)j * kMaxD + i];
-            __syncthreads();
-            // s = p_j . q  = hp_j . b
-            double s = 0;
-            for (int i = lane; i < m; i += WAVE) s += hp[(int64_t)j * kMaxD + i] * b[i];
-            s = wave_sum(s);
-            for (int i = lane; i < m; i += WAVE) b[i] -= s * B[(int64_t)j * kMaxD + i];
-            __syncthreads();
-        }
-        // eta = a^T Gxy b, |p|^2 = a^T Gxx a, |q|^2 = b^T Gyy b
         double eta = 0, pn = 0, qn = 0;
-        for (int i = lane; i < m; i += WAVE) {
-            double ty = 0, tx = 0, tq = 0;
-            for (int k = 0; k < m; ++k) {
-                ty += gxy(i, k) * b[k];
-                tx += gxx(i, k) * a[k];
-                tq += gyy(i, k) * b[k];
-            }
-            eta += a[i] * ty;
-            pn += a[i] * tx;
-            qn += b[i] * tq;
+        for (int i = tid; i <= l; i += nt) {
+            eta += al[i] * txy[i];
+            pn += al[i] * txx[i];
+            qn += bl[i] * tyy[i];
         }
-        eta = wave_sum(eta);
-        pn = sqrt(fmax(wave_sum(pn), 0.0));
-        qn = sqrt(fmax(wave_sum(qn), 0.0));
+        eta = block_sum<256>(eta, red);
+        pn = sqrt(fmax(block_sum<256>(pn, red), 0.0));
+        qn = sqrt(fmax(block_sum<256>(qn, red), 0.0));
         const double xn = sqrt(gxx(l, l)), yn = sqrt(gyy(l, l));
-        if (eta == 0.0 || fabs(eta) <= cos_tol * pn * qn || pn <= dep_tol * xn || qn <= dep_tol * yn) {
-            __syncthreads();
-            continue;
-        }
+        if (eta == 0.0 || fabs(eta) <= cos_tol * pn * qn || pn <= dep_tol * xn || qn <= dep_tol * yn) continue;
         const double sl = sqrt(fabs(eta));
         const double rl = eta < 0 ? -sl : sl;
-        for (int i = lane; i < m; i += WAVE) {
-            a[i] /= rl;
-            b[i] /= sl;
-            A[(int64_t)np * kMaxD + i] = a[i];
-            B[(int64_t)np * kMaxD + i] = b[i];
+        for (int i = tid; i < m; i += nt) {
+            const double av = (i <= l) ? al[i] / rl : 0.0, bv = (i <= l) ? bl[i] / sl : 0.0;
+            Aout[(int64_t)np * kMaxD + i] = av;
+            Bout[(int64_t)np * kMaxD + i] = bv;
+            txy[i] /= sl;   // Gxy b_l with the scaled b_l
+            u[i] /= rl;     // Gxy^T a_l with the scaled a_l
         }
         __syncthreads();
-        // hq_np[i] = sum_k Gxy(i,k) b_k  (q_np . x_i);  hp_np[i] = sum_k a_k Gxy(k,i)  (p_np . y_i)
-        for (int i = lane; i < m; i += WAVE) {
-            double t1 = 0, t2 = 0;
-            for (int k = 0; k < m; ++k) {
-                t1 += gxy(i, k) * b[k];
-                t2 += a[k] * gxy(k, i);
-            }
-            hq[np * kMaxD + i] = t1;
-            hp[(int64_t)np * kMaxD + i] = t2;
+        for (int i = tid; i <= l; i += nt) {
+            A[(int64_t)l * kMaxD + i] = al[i] / rl;
+            B[(int64_t)l * kMaxD + i] = bl[i] / sl;
         }
-        __syncthreads();
         ++np;
+        __syncthreads();
+        for (int j = l + 1 + wid; j < m; j += nt / WAVE) {
+            double r = 0, s = 0;
+            for (int i = lane; i <= j; i += WAVE) {
+                r += txy[i] * A[(int64_t)j * kMaxD + i];
+                s += u[i] * B[(int64_t)j * kMaxD + i];
+            }
+            r = wsum(r);
+            s = wsum(s);
+            if (lane == 0) {
+                rr[j] = r;
+                ss[j] = s;
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (l + 1) * (m - l - 1); idx += nt) {
+            const int i = idx % (l + 1), j = l + 1 + idx / (l + 1);
+            A[(int64_t)j * kMaxD + i] -= rr[j] * A[(int64_t)l * kMaxD + i];
+            B[(int64_t)j * kMaxD + i] -= ss[j] * B[(int64_t)l * kMaxD + i];
+        }
+        __syncthreads();
     }
-    if (lane == 0) status[ST_NKEPT] = np;
+    if (tid == 0) status[ST_NKEPT] = np;
 }
 
 }  // namespace
 
 hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh, int64_t ldh, double* lam,
-                      double* Xh, double* Yh, double* scratch, int* status) {
+                      double* Xh, double* Yh, double* scratch, int* status, double* work, size_t work_elems) {
     if (d < 1 || d > kMaxD) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(chol2_kernel, dim3(2), dim3(1024), 0, st, d, Kh, Mh, ldh, scratch, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // B = L2^T L1 into scratch + 3 D2
+    Seg a{scratch + D2, kMaxD, d}, b{scratch, kMaxD, d};
+    e = gemm_tn(st, d, d, d, &a, 1, &b, 1, scratch + 3 * D2, kMaxD, 1.0, 0, work, work_elems);
+    if (e != hipSuccess) return e;
+    double* T = scratch + 2 * D2;
     if (d <= 32)
-        hipLaunchKernelGGL(small_lrep_kernel<32>, dim3(1), dim3(32 * 8), 0, st, d, Kh, Mh, ldh, lam, Xh, Yh, scratch,
-                           status);
+        hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(32 * 8), 0, st, d, scratch, lam, Yh, T, status);
     else if (d <= 64)
-        hipLaunchKernelGGL(small_lrep_kernel<64>, dim3(1), dim3(64 * 8), 0, st, d, Kh, Mh, ldh, lam, Xh, Yh, scratch,
-                           status);
+        hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(64 * 8), 0, st, d, scratch, lam, Yh, T, status);
     else
-        hipLaunchKernelGGL(small_lrep_kernel<128>, dim3(1), dim3(128 * 8), 0, st, d, Kh, Mh, ldh, lam, Xh, Yh,
-                           scratch, status);
-    return hipGetLastError();
+        hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(128 * 8), 0, st, d, scratch, lam, Yh, T, status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // X^ = L2 T
+    Seg l2{scratch + D2, kMaxD, d};
+    return gemm_nn(st, d, d, d, &l2, 1, T, kMaxD, Xh, kMaxD, 1.0, 0.0, work, work_elems);
 }
 
 hipError_t step5_pq(hipStream_t st, int d, int hi, const double* Xh, const double* Yh, const int* win, int nw,
-                    double* Ph, double* Qh, double* scratch, int* status, double cos_tol, double dep_tol) {
-    if (nw > 64 || d > kMaxD) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(step5_kernel, dim3(1), dim3(256), 0, st, d, hi, Xh, Yh, win, nw, Ph, Qh, scratch, status,
-                       cos_tol, dep_tol);
+                    double* Ph, double* Qh, double* scratch, int* status, double cos_tol, double dep_tol,
+                    double* work, size_t work_elems) {
+    if (nw > 64 || nw < 1 || d > kMaxD || hi > d) return hipErrorInvalidValue;
+    double* V = scratch;
+    double* U = scratch + kMaxD * 64;
+    double* C = scratch + 2 * kMaxD * 64;
+    double* n0 = scratch + 3 * kMaxD * 64;
+    hipLaunchKernelGGL(step5_gather_kernel, dim3(nw), dim3(256), 0, st, d, Xh, Yh, win, nw, V, U, n0);
+    hipError_t e = hipGetLastError();
+    for (int side = 0; side < 2 && e == hipSuccess && hi > 0; ++side) {
+        double* Vs = side == 0 ? V : U;
+        Seg basis{side == 0 ? Xh : Yh, kMaxD, hi};
+        Seg dual{side == 0 ? Yh : Xh, kMaxD, hi};
+        Seg vs{Vs, kMaxD, nw};
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            e = gemm_tn(st, d, hi, nw, &dual, 1, &vs, 1, C, kMaxD, 1.0, 0, work, work_elems);
+            if (e == hipSuccess)
+                e = gemm_nn(st, d, nw, hi, &basis, 1, C, kMaxD, Vs, kMaxD, -1.0, 1.0, work, work_elems);
+        }
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(small_mgs_kernel, dim3(1), dim3(256), 0, st, d, nw, V, U, n0, Ph, Qh, status, cos_tol,
+                       dep_tol);
     return hipGetLastError();
 }
 
 hipError_t coef_mgs(hipStream_t st, int m, const double* G, int64_t ldg, double* A, double* B, int* status,
-                    double cos_tol, double dep_tol) {
+                    double cos_tol, double dep_tol, double* scratch) {
     if (m > kMaxD) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(coef_mgs_kernel, dim3(1), dim3(64), 0, st, m, G, ldg, A, B, status, cos_tol, dep_tol);
+    hipLaunchKernelGGL(coef_mgs_kernel, dim3(1), dim3(256), 0, st, m, G, ldg, scratch, scratch + D2, A, B, status,
+                       cos_tol, dep_tol);
     return hipGetLastError();
 }
 

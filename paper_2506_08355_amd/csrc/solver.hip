@@ -26,10 +26,22 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
 #include "internal.hpp"
+
+#define CK(x)                                  \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return dev_fail(e_, #x); \
+    } while (0)
+#define CR(x)                     \
+    do {                          \
+        int r_ = (x);             \
+        if (r_ != LREP_OK) return r_; \
+    } while (0)
 
 namespace lrep {
 
@@ -57,7 +69,7 @@ struct Solver {
     int64_t n;
     int b, w, cap, nev, r0;
     double tol;
-    lrep_solve_opts_t o;
+    lrep_solve_opts_t o{};
     // device buffers
     DevBuf bX[2], bY[2], bKX[2], bMY[2];
     DevBuf Xc, Yc;
@@ -73,9 +85,50 @@ struct Solver {
     HostStatus* hs = nullptr;
     std::string err;
     lrep_stats_t stats{};
+    // profiling of the CG applies: event pairs, column counts and the CG
+    // "any column active" flag logged on the device just before each apply
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_cols;
+    DevBuf prof_log;
+    static constexpr int kProfMax = 1 << 16;
 
     ~Solver() {
         if (hs) (void)hipHostFree(hs);
+        for (auto e : prof_ev) (void)hipEventDestroy(e);
+    }
+
+    hipEvent_t* prof_next(int cols) {
+        const size_t i = prof_cols.size();
+        if (!prof_log.p || i >= (size_t)kProfMax) return nullptr;
+        while (prof_ev.size() < 2 * (i + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            prof_ev.push_back(e);
+        }
+        int* log = reinterpret_cast<int*>(prof_log.p);
+        if (hipMemcpyAsync(log + i, cg_any, sizeof(int), hipMemcpyDeviceToDevice, st) != hipSuccess) return nullptr;
+        prof_cols.push_back(cols);
+        return &prof_ev[2 * i];
+    }
+
+    int prof_collect() {
+        const size_t k = prof_cols.size();
+        if (k == 0) return LREP_OK;
+        std::vector<int> log(k);
+        CK(hipMemcpyAsync(log.data(), prof_log.p, k * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        const double nn = (double)n;
+        for (size_t i = 0; i < k; ++i) {
+            if (!log[i]) continue;   // every column had converged: the launch returned at once
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, prof_ev[2 * i], prof_ev[2 * i + 1]));
+            const double c = prof_cols[i];
+            stats.prof_launches++;
+            stats.prof_ms += ms;
+            stats.prof_bytes += 8.0 * nn * nn + 16.0 * nn * c;
+            stats.prof_flops += 2.0 * nn * nn * c;
+        }
+        return LREP_OK;
     }
 
     int fail(int code, const char* what) {
@@ -87,16 +140,6 @@ struct Solver {
         return LREP_EDEVICE;
     }
 
-#define CK(x)                                  \
-    do {                                       \
-        hipError_t e_ = (x);                   \
-        if (e_ != hipSuccess) return dev_fail(e_, #x); \
-    } while (0)
-#define CR(x)                     \
-    do {                          \
-        int r_ = (x);             \
-        if (r_ != LREP_OK) return r_; \
-    } while (0)
 
     int alloc() {
         Ctx* c = op->ctx;
@@ -131,7 +174,7 @@ struct Solver {
         };
         size_t oKh = carve(D2), oMh = carve(D2), oS = carve(D2), oXh = carve(D2), oYh = carve(D2),
                olam = carve(kMaxD), oeps = carve(kMaxD), olamw = carve(kMaxD), oPh = carve(kMaxD * 64),
-               oQh = carve(kMaxD * 64), oA = carve(D2), oB = carve(2 * D2), oscr = carve(3 * D2),
+               oQh = carve(kMaxD * 64), oA = carve(D2), oB = carve(2 * D2), oscr = carve(4 * D2),
                oG = carve(4 * D2), oC = carve((size_t)kproj * std::max(kMaxD, cw)),
                oT = carve((size_t)std::max<int64_t>(rank, 1) * kMaxD), opart = carve((size_t)256 * kMaxD * 4),
                orr = carve(kMaxD), obb = carve(kMaxD), oal = carve(kMaxD), obe = carve(kMaxD), oom = carve(8);
@@ -154,6 +197,7 @@ struct Solver {
         napplies = reinterpret_cast<unsigned long long*>(tickets + 8);
         CK(hipMemsetAsync(ismall.p, 0, ismall.bytes, st));
         CK(hipHostMalloc((void**)&hs, sizeof(HostStatus), hipHostMallocDefault));
+        if (o.profile) CR(prof_log.alloc(c, kProfMax * sizeof(int)));
         return LREP_OK;
     }
 
@@ -176,8 +220,8 @@ struct Solver {
         return s;
     }
 
-    int apply(int which, const double* X, int cols, double* Y, const int* flag = nullptr) {
-        return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag);
+    int apply(int which, const double* X, int cols, double* Y, const int* flag = nullptr, hipEvent_t* ev = nullptr) {
+        return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev);
     }
 
     // solution of A x_j = rhs_j (which: 0 = K, 1 = M) into cgX; `maxit` CG steps
@@ -185,7 +229,8 @@ struct Solver {
         CgState s = cg_state(1, which);
         CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
         for (int it = 0; it < maxit; ++it) {
-            CR(apply(which, cgP.p, nw, cgQ.p, cg_any));
+            hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw) : nullptr;
+            CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
             CK(lrep::cg_alpha(st, (int)n, nw, s));
             CK(cg_update(st, (int)n, nw, s, cgtol));
             CK(cg_direction(st, (int)n, nw, s));
@@ -240,7 +285,7 @@ struct Solver {
         const int64_t ldg = 2 * kMaxD;
         // pass 1
         CR(gram(segs({{X, n, m}, {Y, n, m}}), segs({{X, n, m}, {Y, n, m}}), G, ldg, 0));
-        CK(coef_mgs(st, m, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF));
+        CK(coef_mgs(st, m, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF, scr));
         CR(read_status());
         const int k1 = hs->status[ST_NKEPT];
         stats.mgs_drops += m - k1;
@@ -249,7 +294,7 @@ struct Solver {
         CR(prod(segs({{Y, n, m}}), Bcoef, kMaxD, k1, tY.p, n, 1.0, 0.0));
         // pass 2
         CR(gram(segs({{tX.p, n, k1}, {tY.p, n, k1}}), segs({{tX.p, n, k1}, {tY.p, n, k1}}), G, ldg, 0));
-        CK(coef_mgs(st, k1, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF));
+        CK(coef_mgs(st, k1, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF, scr));
         CR(read_status());
         const int k2 = hs->status[ST_NKEPT];
         stats.mgs_drops += k1 - k2;
@@ -300,7 +345,8 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     int c = 0;
     const int lock_unit = std::min(2 * w, b);
     int it = 0;
-    int restores_in_row = 0;
+    const bool trace = std::getenv("LREP_TRACE") != nullptr;
+    bool just_restored = false;
     int rc = LREP_ENOTCONV;
     std::vector<double> epsc;
     while (it < o.maxit) {
@@ -325,15 +371,17 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CR(gram(segs({{V, n, d}}), segs({{MV, n, d}}), Mh, kMaxD, 1));
         CR(gram(segs({{U, n, d}}), segs({{V, n, d}}), S, kMaxD, 0));
         CK(max_offidentity(st, d, S, kMaxD, offmax));
-        CK(small_lrep(st, d, Kh, Mh, kMaxD, lam, Xh, Yh, scr, status));
+        CK(small_lrep(st, d, Kh, Mh, kMaxD, lam, Xh, Yh, scr, status, gwork.p, GEMM_WORK_ELEMS));
         const int nr = std::min(b, d);
         auto pull = [&](int g0, int g1, int col0) -> int {
             if (g1 <= g0) return LREP_OK;
             const int k = g1 - g0;
-            CR(prod(segs({{U, n, d}}), Xh + (size_t)g0 * kMaxD, kMaxD, k, NX + (size_t)col0 * n, n, 1.0, 0.0));
-            CR(prod(segs({{V, n, d}}), Yh + (size_t)g0 * kMaxD, kMaxD, k, NY + (size_t)col0 * n, n, 1.0, 0.0));
-            CR(prod(segs({{KU, n, d}}), Xh + (size_t)g0 * kMaxD, kMaxD, k, NKX + (size_t)col0 * n, n, 1.0, 0.0));
-            CR(prod(segs({{MV, n, d}}), Yh + (size_t)g0 * kMaxD, kMaxD, k, NMY + (size_t)col0 * n, n, 1.0, 0.0));
+            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+            const double* B4[4] = {Xh + (size_t)g0 * kMaxD, Yh + (size_t)g0 * kMaxD, Xh + (size_t)g0 * kMaxD,
+                                   Yh + (size_t)g0 * kMaxD};
+            double* C4[4] = {NX + (size_t)col0 * n, NY + (size_t)col0 * n, NKX + (size_t)col0 * n,
+                             NMY + (size_t)col0 * n};
+            CK(gemm_nn_batch(st, (int)n, k, d, 4, A4, B4, kMaxD, C4, n, 1.0, 0.0));
             return LREP_OK;
         };
         CR(pull(0, nr, 0));
@@ -344,17 +392,25 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CK(hipMemcpyAsync(&hs->offmax, offmax, sizeof(double), hipMemcpyDeviceToHost, st));
         CR(read_status());
         if (hs->status[ST_NOTSPD]) return fail(LREP_ENOTSPD, "Cholesky of a projected matrix failed");
-        // biorthogonality monitor: restore U^T V = I and redo the iteration
-        if (!(hs->offmax <= o.rebiorth_tol)) {
-            if (!std::isfinite(hs->offmax)) return fail(LREP_ENUMERIC, "non-finite value in U^T V");
+        if (trace) {
+            double em = 0;
+            for (int g = 0; g < nr; ++g) em = std::max(em, hs->eps[g]);
+            std::fprintf(stderr, "[lrep] it=%d d=%d locked=%d offmax=%.3e max_eps=%.3e lam0=%.15e sweeps=%d\n", it,
+                         d, c, hs->offmax, em, hs->lam[0], hs->status[ST_SWEEPS]);
+        }
+        // biorthogonality monitor: restore U^T V = I and redo the iteration (the
+        // check is skipped on the pass right after a restore, as the check
+        // happens once per iteration before the projection)
+        if (!std::isfinite(hs->offmax)) return fail(LREP_ENUMERIC, "non-finite value in U^T V");
+        if (!just_restored && !(hs->offmax <= o.rebiorth_tol)) {
             --it;
             stats.rebiorth++;
-            if (++restores_in_row > 3) return fail(LREP_EBREAKDOWN, "biorthogonality cannot be restored");
+            just_restored = true;
             CR(block_mgs(U, V, d, U, V, &kept));
             d = kept;
             continue;
         }
-        restores_in_row = 0;
+        just_restored = false;
         for (int g = 0; g < nr; ++g)
             if (!std::isfinite(hs->eps[g]) || !std::isfinite(hs->lam[g]))
                 return fail(LREP_ENUMERIC, "non-finite Ritz value or residual");
@@ -410,14 +466,18 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CK(hipMemcpyAsync(wincol, wcol.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st));
         CK(hipMemcpyAsync(lamw, lw.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st));
         // Step 5
-        CK(step5_pq(st, d, hi, Xh, Yh, win, nw, Ph, Qh, scr, status, MGS_COS_TOL, MGS_DEP_TOL));
+        CK(step5_pq(st, d, hi, Xh, Yh, win, nw, Ph, Qh, scr, status, MGS_COS_TOL, MGS_DEP_TOL, gwork.p, GEMM_WORK_ELEMS));
         CR(read_status());
         const int np = hs->status[ST_NP];
         stats.mgs_drops += nw - np;
         double* Pt = NX + (size_t)hi * n;
         double* Qt = NY + (size_t)hi * n;
-        CR(prod(segs({{U, n, d}}), Ph, kMaxD, np, Pt, n, 1.0, 0.0));
-        CR(prod(segs({{V, n, d}}), Qh, kMaxD, np, Qt, n, 1.0, 0.0));
+        {
+            const Seg A2[2] = {{U, n, d}, {V, n, d}};
+            const double* B2[2] = {Ph, Qh};
+            double* C2[2] = {Pt, Qt};
+            CK(gemm_nn_batch(st, (int)n, np, d, 2, A2, B2, kMaxD, C2, n, 1.0, 0.0));
+        }
         // Step 6: block Gauss-Seidel sweeps with CG
         for (int j = 0; j < o.ngs; ++j) {
             CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, n, NX, NMY, n, wincol, lamw, rhs.p, n));
@@ -452,6 +512,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     stats.applies_M += (int64_t)hs->napplies[1];
     stats.iterations = it;
     stats.n_converged = c;
+    if (o.profile) CR(prof_collect());
     double me = 0;
     for (double e : epsc) me = std::max(me, e);
     stats.max_eps = me;
@@ -475,14 +536,21 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
 }  // namespace
 
 int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy,
-             double* work, size_t work_elems, double* small, const int* active_flag) {
+             double* work, size_t work_elems, double* small, const int* active_flag, hipEvent_t* ev) {
     if (cols <= 0) return LREP_OK;
     const bool useK = (which == 0) != op->null_on_M();
     hipError_t e = hipSuccess;
     if (op->kind == 0) {
-        Seg A{useK ? op->K : op->M, op->ld, (int)op->n};
-        e = gemm_nn(st, (int)op->n, cols, (int)op->n, &A, 1, X, ldx, Y, ldy, 1.0, 0.0, work, work_elems, nullptr,
-                    nullptr, 0, 0, active_flag);
+        const double* Ad = useK ? op->K : op->M;
+        const bool stream_ok = cols <= 32 && (op->ld % 2) == 0 && (reinterpret_cast<uintptr_t>(Ad) % 16) == 0;
+        if (stream_ok) {
+            e = dense_apply_narrow(st, (int)op->n, cols, (int)op->n, Ad, op->ld, X, ldx, Y, ldy, 1.0, 0.0, work,
+                                   work_elems, active_flag, ev);
+        } else {
+            Seg A{Ad, op->ld, (int)op->n};
+            e = gemm_nn(st, (int)op->n, cols, (int)op->n, &A, 1, X, ldx, Y, ldy, 1.0, 0.0, work, work_elems,
+                        nullptr, nullptr, 0, 0, active_flag, ev);
+        }
     } else if (useK) {
         e = diag_scale(st, (int)op->n, cols, op->delta, X, ldx, Y, ldy, active_flag);
     } else {

@@ -53,13 +53,15 @@ int lrep_test_small_lrep(lrep_ctx_t ctx, int d, const double* Kh, const double* 
                          double* Xh, double* Yh) {
     if (!ctx || d < 1 || d > kMaxD || ldh < d) return LREP_EINVAL;
     (void)hipSetDevice(ctx->device);
-    DevBuf scr, st;
-    int rc = scr.alloc(ctx, 3 * kMaxD * kMaxD * sizeof(double));
+    DevBuf scr, st, work;
+    const size_t welems = size_t(1) << 20;
+    int rc = scr.alloc(ctx, 4 * kMaxD * kMaxD * sizeof(double));
     if (rc == LREP_OK) rc = st.alloc(ctx, ST_COUNT * sizeof(int));
+    if (rc == LREP_OK) rc = work.alloc(ctx, welems * sizeof(double));
     if (rc != LREP_OK) return rc;
     int* status = reinterpret_cast<int*>(st.p);
     hipError_t e = hipMemsetAsync(status, 0, ST_COUNT * sizeof(int), ctx->stream);
-    if (e == hipSuccess) e = small_lrep(ctx->stream, d, Kh, Mh, ldh, lam, Xh, Yh, scr.p, status);
+    if (e == hipSuccess) e = small_lrep(ctx->stream, d, Kh, Mh, ldh, lam, Xh, Yh, scr.p, status, work.p, welems);
     rc = finish(ctx, e);
     if (rc != LREP_OK) return rc;
     int hs[ST_COUNT];

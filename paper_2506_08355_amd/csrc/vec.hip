@@ -60,19 +60,21 @@ __global__ __launch_bounds__(NT) void residual_kernel(int n, int cols, int nchun
         p[2] = sx;
         p[3] = sy;
     }
-    if (last_block_arrives(ticket, gridDim.x * gridDim.y)) {
-        for (int c = threadIdx.x; c < cols; c += NT) {
-            double t1 = 0, t2 = 0, tx = 0, ty = 0;
-            const double* p = part + (int64_t)c * nchunks * 4;
-            for (int k = 0; k < nchunks; ++k) {
-                t1 += p[4 * k];
-                t2 += p[4 * k + 1];
-                tx += p[4 * k + 2];
-                ty += p[4 * k + 3];
-            }
-            const double lc = lam[c];
-            eps[c] = sqrt(t1 + t2) / ((1.0 + lc) * sqrt(tx + ty));
+}
+
+__global__ __launch_bounds__(NT) void residual_fin_kernel(int cols, int nchunks, const double* __restrict__ part,
+                                                          const double* __restrict__ lam, double* __restrict__ eps) {
+    for (int c = threadIdx.x; c < cols; c += NT) {
+        double t1 = 0, t2 = 0, tx = 0, ty = 0;
+        const double* p = part + (int64_t)c * nchunks * 4;
+        for (int k = 0; k < nchunks; ++k) {
+            t1 += p[4 * k];
+            t2 += p[4 * k + 1];
+            tx += p[4 * k + 2];
+            ty += p[4 * k + 3];
         }
+        const double lc = lam[c];
+        eps[c] = sqrt(t1 + t2) / ((1.0 + lc) * sqrt(tx + ty));
     }
 }
 
@@ -94,22 +96,22 @@ __global__ __launch_bounds__(NT) void cg_init_kernel(int n, int w, int nchunks, 
     }
     acc = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
-    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
-        __shared__ int any;
-        if (threadIdx.x == 0) any = 0;
-        __syncthreads();
-        for (int c = threadIdx.x; c < w; c += NT) {
-            double t = 0;
-            for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
-            s.rr[c] = t;
-            s.bb[c] = t;
-            const int a = t > tol * tol * t ? 1 : 0;
-            s.active[c] = a;
-            if (a) atomicOr(&any, 1);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) *s.any_active = any;
+}
+
+// one block: rr = bb = |b|^2, active = rr > tol^2 bb, any_active
+__global__ __launch_bounds__(64) void cg_init_fin_kernel(int w, int nchunks, CgState s, double tol) {
+    int any = 0;
+    for (int c = threadIdx.x; c < w; c += 64) {
+        double t = 0;
+        for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
+        s.rr[c] = t;
+        s.bb[c] = t;
+        const int a = t > tol * tol * t ? 1 : 0;
+        s.active[c] = a;
+        any |= a;
     }
+    any = __any(any) ? 1 : 0;
+    if (threadIdx.x == 0) *s.any_active = any;
 }
 
 __global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks, CgState s) {
@@ -124,26 +126,28 @@ __global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks,
         for (int i = r0 + threadIdx.x; i < r1; i += NT) acc += s.P[off + i] * s.Q[off + i];
     acc = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
-    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
-        if (threadIdx.x == 0) {
-            unsigned long long na = 0;
-            for (int c = 0; c < w; ++c) na += s.active[c] ? 1ull : 0ull;
-            *s.napplies += na;
+}
+
+// one block: alpha = rr / (p . q); a column with p^T A p <= 0 stops
+__global__ __launch_bounds__(64) void cg_alpha_fin_kernel(int w, int nchunks, CgState s) {
+    if (*s.any_active == 0) return;
+    int na = 0;
+    for (int c = threadIdx.x; c < w; c += 64) {
+        double a = 0.0;
+        if (s.active[c]) {
+            ++na;
+            double pq = 0;
+            for (int k = 0; k < nchunks; ++k) pq += s.part[(int64_t)c * nchunks + k];
+            if (pq > 0.0)
+                a = s.rr[c] / pq;
+            else
+                s.active[c] = 0;   // breakdown: p^T A p <= 0 (singular operator)
         }
-        __syncthreads();
-        for (int c = threadIdx.x; c < w; c += NT) {
-            double a = 0.0;
-            if (s.active[c]) {
-                double pq = 0;
-                for (int k = 0; k < nchunks; ++k) pq += s.part[(int64_t)c * nchunks + k];
-                if (pq > 0.0)
-                    a = s.rr[c] / pq;
-                else
-                    s.active[c] = 0;   // breakdown: p^T A p <= 0 (singular operator)
-            }
-            s.alpha[c] = a;
-        }
+        s.alpha[c] = a;
     }
+    // count the columns that received an apply (fixed-order wave sum of ints)
+    for (int off = 32; off >= 1; off >>= 1) na += __shfl_xor(na, off, 64);
+    if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
 }
 
 __global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol) {
@@ -165,24 +169,25 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks
     }
     acc = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
-    if (last_block_arrives(s.ticket, gridDim.x * gridDim.y)) {
-        __shared__ int any;
-        if (threadIdx.x == 0) any = 0;
-        __syncthreads();
-        for (int c = threadIdx.x; c < w; c += NT) {
-            if (s.active[c]) {
-                double t = 0;
-                for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
-                s.beta[c] = t / s.rr[c];
-                s.rr[c] = t;
-                const int a = t > tol * tol * s.bb[c] ? 1 : 0;
-                s.active[c] = a;
-                if (a) atomicOr(&any, 1);
-            }
+}
+
+// one block: beta, rr, active (relative residual test), any_active
+__global__ __launch_bounds__(64) void cg_update_fin_kernel(int w, int nchunks, CgState s, double tol) {
+    if (*s.any_active == 0) return;
+    int any = 0;
+    for (int c = threadIdx.x; c < w; c += 64) {
+        if (s.active[c]) {
+            double t = 0;
+            for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
+            s.beta[c] = t / s.rr[c];
+            s.rr[c] = t;
+            const int a = t > tol * tol * s.bb[c] ? 1 : 0;
+            s.active[c] = a;
+            any |= a;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) *s.any_active = any;
     }
+    any = __any(any) ? 1 : 0;
+    if (threadIdx.x == 0) *s.any_active = any;
 }
 
 __global__ __launch_bounds__(NT) void cg_direction_kernel(int n, int w, CgState s) {
@@ -341,6 +346,7 @@ hipError_t residual_eps(hipStream_t st, int n, int cols, const double* X, const 
     while ((size_t)nch * cols * 4 > part_elems && nch > 1) nch /= 2;
     hipLaunchKernelGGL(residual_kernel, dim3(nch, cols), dim3(NT), 0, st, n, cols, nch, X, Y, KX, MY, ld, lam, eps,
                        part, ticket);
+    hipLaunchKernelGGL(residual_fin_kernel, dim3(1), dim3(NT), 0, st, cols, nch, part, lam, eps);
     return hipGetLastError();
 }
 
@@ -353,16 +359,19 @@ static int cg_chunks(int n, int w, const CgState& s) {
 hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb, double tol) {
     const int nch = cg_chunks(n, w, s);
     hipLaunchKernelGGL(cg_init_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, B, ldb, tol);
+    hipLaunchKernelGGL(cg_init_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
     const int nch = cg_chunks(n, w, s);
     hipLaunchKernelGGL(cg_alpha_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s);
+    hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
     return hipGetLastError();
 }
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol) {
     const int nch = cg_chunks(n, w, s);
     hipLaunchKernelGGL(cg_update_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, tol);
+    hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s) {

@@ -117,10 +117,13 @@ def test_block_mgs_drops_dependent_columns(ctx):
     np.testing.assert_allclose(P.T @ Q, np.eye(5), atol=1e-12)
 
 
-@pytest.mark.parametrize("kind", ["dense", "lowrank", "dense_swap"])
-def test_operator_apply(ctx, kind):
+@pytest.mark.parametrize("kind,n,cols", [("dense", 1500, 19), ("dense", 1501, 32), ("dense", 4096, 32),
+                                         ("dense", 700, 48), ("lowrank", 1500, 19), ("dense_swap", 1500, 19)])
+def test_operator_apply(ctx, kind, n, cols):
+    """Dense applies with <= 32 columns and an even leading dimension take the
+    streaming kernel (ragged row tiles at 1500), odd n and wide blocks the
+    tiled product."""
     rng = np.random.default_rng(5)
-    n, cols = 1500, 19
     Xh = rng.standard_normal((n, cols))
     if kind == "lowrank":
         f = gen.casida_factors(n, 24, 3)
