@@ -1,26 +1,28 @@
-// Streaming FP64 MFMA block apply Y = A X for a dense operator A (n x n,
-// column-major) and a narrow block X (n x q, q <= 32): the CG inner solves of
+// Streaming FP64 MFMA block apply Y = A X for a dense operator A (m x p,
+// column-major) and a narrow block X (p x q, q <= 32): the CG inner solves of
 // Step 6 (block Gauss-Seidel), where every launch reads the whole operator
-// once and the product sits at the HBM/FP64-MFMA ridge (2 n^2 q flops over
-// 8 n^2 bytes: q/4 flop/byte).
+// once and the product sits at the HBM/FP64-MFMA ridge (2 m p q flops over
+// 8 m p bytes: q/4 flop/byte against a ridge of 9.8 on MI355X).
 //
 // Design for gfx950:
-//  * no LDS and no barriers in the main loop.  Each wavefront owns 32 rows
-//    and streams its A panel straight from HBM into registers with 16-byte
-//    loads (two consecutive rows per lane), software-pipelined PF k-steps
-//    ahead in two register halves, so that ~2 * PF KiB per wavefront are in
-//    flight;
-//  * the block X is first packed k-major (n x 32, zero-padded) so that the
-//    MFMA B fragments are also contiguous 16-byte loads; the 2 KiB it takes
-//    per k-step of 32 rows is reused by every wavefront through L1/L2;
-//  * two row fragments x two column fragments = four v_mfma_f64_16x16x4
-//    per k-step.  Fragment (fm, fn), row i, column c maps to row 2i + fm and
-//    column 2c + fn of the wavefront tile (the interleave that the 16-byte
-//    loads produce);
+//  * no LDS and no barriers in the main loop.  Each wavefront (one per
+//    workgroup) owns WR = 64 rows and streams its A panel straight from HBM
+//    into registers with 16-byte loads (rows 2c, 2c+1 and 32+2c, 33+2c for
+//    lane column c), software-pipelined PF k-steps ahead in two register
+//    halves.  The loads of interior tiles carry no per-lane conditions (the
+//    step index is clamped and the surplus steps multiply by a zero B
+//    fragment), so the compiler can wait on exactly the half it needs;
+//  * the block X is first packed k-major (p x 32, zero-padded) so that the
+//    MFMA B fragments are contiguous 16-byte loads too, shared by all
+//    wavefronts through L1/L2;
+//  * four row fragments x two column fragments = eight
+//    v_mfma_f64_16x16x4_f64 per k-step.  Fragment (fm, fn), row i, column c
+//    is row 32 (fm / 2) + 2 i + (fm % 2) and column 2 c + fn of the tile;
 //  * the k dimension is split over workgroups for occupancy; each wavefront
-//    writes its 32 x 32 partial tile in lane order (128 contiguous bytes per
+//    writes its 64 x 32 partial tile in lane order (256 contiguous bytes per
 //    lane) and a second kernel sums the splits in a fixed order (bitwise
-//    reproducible) while scattering to the column-major result.
+//    reproducible) and writes the column-major result.  For the CG it also
+//    forms the per-tile, per-column sums of p . (A p).
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -28,135 +30,278 @@ namespace lrep {
 
 namespace {
 
-constexpr int NT = 256;   // 4 wavefronts x 32 rows = 128 rows per workgroup
-constexpr int PF = 4;     // k-steps (4 columns each) per prefetch half
+constexpr int WR = 64;       // rows per wavefront tile
+constexpr int PF = 4;        // k-steps (4 columns each) per prefetch half
+constexpr int TV = WR / 2;   // values per lane in a tile (WR x 32 / 64 lanes)
 
-__global__ __launch_bounds__(NT) void pack_kmajor_kernel(int n, int q, const double* __restrict__ X, int64_t ldx,
-                                                         double* __restrict__ Pt, const int* __restrict__ flag) {
+// Pt (p x 32, row k = X[k, 0:32], zero-padded) from X (p x q, ld ldx)
+__global__ __launch_bounds__(256) void pack_kmajor_kernel(int p, int q, const double* __restrict__ X, int64_t ldx,
+                                                          double* __restrict__ Pt, const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
-    const int64_t total = (int64_t)n * 32;
-    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
-        const int k = (int)(idx / 32), c = (int)(idx % 32);
-        Pt[idx] = c < q ? X[(int64_t)c * ldx + k] : 0.0;
+    __shared__ double tile[64][33];
+    const int r0 = blockIdx.x * 64;
+    for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
+        const int c = idx / 64, i = idx % 64;
+        tile[i][c] = (c < q && r0 + i < p) ? X[(int64_t)c * ldx + r0 + i] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
+        const int i = idx / 32, c = idx % 32;
+        if (r0 + i < p) Pt[(int64_t)(r0 + i) * 32 + c] = tile[i][c];
     }
 }
 
-__global__ __launch_bounds__(NT) void apply_stream_kernel(int m, int p, const double* __restrict__ A, int64_t lda,
+// CG search direction fused with the packing: for the active columns
+// p = r + beta p (written back to P, ld n) unless `first`, then Pt = pack(P).
+__global__ __launch_bounds__(256) void cg_dir_pack_kernel(int n, int w, double* __restrict__ P,
+                                                          const double* __restrict__ R,
+                                                          const double* __restrict__ beta,
+                                                          const int* __restrict__ active, int first,
+                                                          double* __restrict__ Pt, const int* __restrict__ flag) {
+    if (*flag == 0) return;
+    __shared__ double tile[64][33];
+    const int r0 = blockIdx.x * 64;
+    for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
+        const int c = idx / 64, i = idx % 64;
+        const int row = r0 + i;
+        double v = 0.0;
+        if (c < w && row < n) {
+            v = P[(int64_t)c * n + row];
+            if (!first && active[c]) {
+                v = R[(int64_t)c * n + row] + beta[c] * v;
+                P[(int64_t)c * n + row] = v;
+            }
+        }
+        tile[i][c] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
+        const int i = idx / 32, c = idx % 32;
+        if (r0 + i < n) Pt[(int64_t)(r0 + i) * 32 + c] = tile[i][c];
+    }
+}
+
+__device__ __forceinline__ void mfma_step(d4 (&acc)[4][2], double2 x, double2 y, double2 b) {
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, b.x, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, b.y, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, b.x, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, b.y, acc[1][1], 0, 0, 0);
+    acc[2][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, b.x, acc[2][0], 0, 0, 0);
+    acc[2][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, b.y, acc[2][1], 0, 0, 0);
+    acc[3][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, b.x, acc[3][0], 0, 0, 0);
+    acc[3][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, b.y, acc[3][1], 0, 0, 0);
+}
+
+__global__ __launch_bounds__(64) void apply_stream_kernel(int m, int p, const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ Pt, int kchunk,
                                                           double* __restrict__ part, const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
-    const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-    const int tile = blockIdx.x * (NT / WAVE) + wid;
-    const int row0 = tile * 32;
-    const int split = blockIdx.z;
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int row0 = tile * WR;
     const int k_begin = split * kchunk;
     const int k_end = min(p, k_begin + kchunk);
-    const int nsteps = (k_end - k_begin + 3) / 4;
+    const int nfull = max(0, (k_end - k_begin) / 4);   // k-steps with all four columns in range
     const int c = lane % 16, kq = lane / 16;
-    const int arow = row0 + 2 * c;
-    const bool full = (arow + 1 < m);
-    d4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-    double2 a0[PF], b0[PF], a1[PF], b1[PF];
-
-    auto load = [&](double2 (&a)[PF], double2 (&b)[PF], int s0) {
+    d4 acc[4][2];
 #pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            const int k = k_begin + (s0 + j) * 4 + kq;
-            double2 av = {0.0, 0.0}, bv = {0.0, 0.0};
-            if (k < k_end) {
-                const double* ap = A + (int64_t)k * lda + arow;
-                if (full) {
-                    av = *reinterpret_cast<const double2*>(ap);
-                } else if (arow < m) {
-                    av.x = ap[0];
-                }
-                bv = *reinterpret_cast<const double2*>(Pt + (int64_t)k * 32 + 2 * c);
+    for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = d4{0.0, 0.0, 0.0, 0.0};
+
+    if (row0 + WR <= m && nfull > 0) {
+        // interior tile: unconditional 16-byte loads, steps clamped to nfull - 1
+        const double* a_base = A + (int64_t)(k_begin + kq) * lda + row0 + 2 * c;
+        const double* b_base = Pt + (int64_t)(k_begin + kq) * 32 + 2 * c;
+        const int64_t a_step = 4 * lda;
+        double2 x0[PF], y0[PF], b0[PF], x1[PF], y1[PF], b1[PF];
+        auto load = [&](double2 (&x)[PF], double2 (&y)[PF], double2 (&b)[PF], int s0) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int s = min(s0 + j, nfull - 1);
+                const double* ap = a_base + (int64_t)s * a_step;
+                x[j] = *reinterpret_cast<const double2*>(ap);
+                y[j] = *reinterpret_cast<const double2*>(ap + 32);
+                b[j] = *reinterpret_cast<const double2*>(b_base + (int64_t)s * 128);
             }
-            a[j] = av;
-            b[j] = bv;
-        }
-    };
-    auto compute = [&](const double2 (&a)[PF], const double2 (&b)[PF]) {
+        };
+        auto compute = [&](const double2 (&x)[PF], const double2 (&y)[PF], const double2 (&b)[PF], int s0) {
 #pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[j].x, acc00, 0, 0, 0);
-            acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[j].y, acc01, 0, 0, 0);
-            acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b[j].x, acc10, 0, 0, 0);
-            acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b[j].y, acc11, 0, 0, 0);
+            for (int j = 0; j < PF; ++j) {
+                const bool live = s0 + j < nfull;
+                const double2 bz = {live ? b[j].x : 0.0, live ? b[j].y : 0.0};
+                mfma_step(acc, x[j], y[j], bz);
+            }
+        };
+        load(x0, y0, b0, 0);
+        for (int s = 0; s < nfull; s += 2 * PF) {
+            load(x1, y1, b1, s + PF);
+            compute(x0, y0, b0, s);
+            load(x0, y0, b0, s + 2 * PF);
+            compute(x1, y1, b1, s + PF);
         }
-    };
-
-    if (row0 < m && nsteps > 0) {
-        load(a0, b0, 0);
-        for (int s = 0; s < nsteps; s += 2 * PF) {
-            if (s + PF < nsteps) load(a1, b1, s + PF);
-            compute(a0, b0);
-            if (s + 2 * PF < nsteps) load(a0, b0, s + 2 * PF);
-            if (s + PF < nsteps) compute(a1, b1);
+    } else if (nfull > 0) {
+        // edge tile: per-lane row checks, no pipelining
+        const int r0 = row0 + 2 * c, r1 = row0 + 32 + 2 * c;
+        for (int s = 0; s < nfull; ++s) {
+            const int k = k_begin + 4 * s + kq;
+            const double* ap = A + (int64_t)k * lda;
+            double2 x = {0.0, 0.0}, y = {0.0, 0.0};
+            if (r0 < m) x.x = ap[r0];
+            if (r0 + 1 < m) x.y = ap[r0 + 1];
+            if (r1 < m) y.x = ap[r1];
+            if (r1 + 1 < m) y.y = ap[r1 + 1];
+            const double2 b = *reinterpret_cast<const double2*>(Pt + (int64_t)k * 32 + 2 * c);
+            mfma_step(acc, x, y, b);
         }
     }
-    if (row0 < m) {
-        const int ntiles = (m + 31) / 32;
-        double* out = part + (((int64_t)split * ntiles + tile) * WAVE + lane) * 16;
-        const d4 accs[4] = {acc00, acc01, acc10, acc11};
+    if (k_begin + 4 * nfull < k_end) {
+        // last partial k-step of the chunk
+        const int k = k_begin + 4 * nfull + kq;
+        const int r0 = row0 + 2 * c, r1 = row0 + 32 + 2 * c;
+        double2 x = {0.0, 0.0}, y = {0.0, 0.0}, b = {0.0, 0.0};
+        if (k < k_end) {
+            const double* ap = A + (int64_t)k * lda;
+            if (r0 < m) x.x = ap[r0];
+            if (r0 + 1 < m) x.y = ap[r0 + 1];
+            if (r1 < m) y.x = ap[r1];
+            if (r1 + 1 < m) y.y = ap[r1 + 1];
+            b = *reinterpret_cast<const double2*>(Pt + (int64_t)k * 32 + 2 * c);
+        }
+        mfma_step(acc, x, y, b);
+    }
+    const int ntiles = (m + WR - 1) / WR;
+    double* out = part + (((int64_t)split * ntiles + tile) * WAVE + lane) * TV;
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
-            *reinterpret_cast<d4*>(out + 4 * f) = accs[f];
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 2; ++fn) *reinterpret_cast<d4*>(out + (fm * 2 + fn) * 4) = acc[fm][fn];
+}
+
+// Sum of the split partial tiles: block (tile, g) of 256 threads writes rows
+// [64 tile, 64 tile + 64) of result columns 8g .. 8g + 7; thread t takes row
+// t % 64 and the column pair 8g + 2 (t / 64) + {0, 1}, which sit next to each
+// other in one lane's partial tile.  The splits are added in a fixed order
+// (bitwise reproducible); all split loads are issued before the adds.
+// C = alpha * sum + beta * C; with P != null also
+// pq[tile * 32 + col] = sum over the tile's rows of P[row, col] * C[row, col].
+constexpr int MAXSPLIT = 16;
+
+__global__ __launch_bounds__(256) void apply_reduce_kernel(int m, int q, int nsplit, const double* __restrict__ part,
+                                                           double* __restrict__ C, int64_t ldc, double alpha,
+                                                           double beta, const double* __restrict__ P, int64_t ldp,
+                                                           double* __restrict__ pq, const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    const int tile = blockIdx.x, g = blockIdx.y;
+    const int ntiles = (m + WR - 1) / WR;
+    const int64_t total = (int64_t)ntiles * WAVE * TV;
+    const int row = threadIdx.x % WR, cp = threadIdx.x / WR;
+    const int col0 = 8 * g + 2 * cp;                 // fn = 0; col0 + 1 has fn = 1
+    const int fm = 2 * (row / 32) + (row % 2);
+    const int t = (row % 32) / 2;                     // 4 r + lane / 16
+    const int lane = 16 * (t % 4) + col0 / 2;
+    const int v0 = 4 * (2 * fm) + t / 4;              // f = 2 fm + fn, v = 4 f + r
+    const double* src = part + (int64_t)tile * WAVE * TV + lane * TV + v0;
+    double x[MAXSPLIT], y[MAXSPLIT];
+#pragma unroll
+    for (int k = 0; k < MAXSPLIT; ++k) {
+        const int kc = k < nsplit ? k : nsplit - 1;
+        x[k] = src[(int64_t)kc * total];
+        y[k] = src[(int64_t)kc * total + 4];
+    }
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXSPLIT; ++k) {
+        if (k < nsplit) {
+            s0 += x[k];
+            s1 += y[k];
+        }
+    }
+    const int grow = tile * WR + row;
+    double p0 = 0.0, p1 = 0.0;
+    if (grow < m) {
+        if (col0 < q) {
+            double o = alpha * s0;
+            if (beta != 0.0) o += beta * C[(int64_t)col0 * ldc + grow];
+            C[(int64_t)col0 * ldc + grow] = o;
+            if (P) p0 = P[(int64_t)col0 * ldp + grow] * o;
+        }
+        if (col0 + 1 < q) {
+            double o = alpha * s1;
+            if (beta != 0.0) o += beta * C[(int64_t)(col0 + 1) * ldc + grow];
+            C[(int64_t)(col0 + 1) * ldc + grow] = o;
+            if (P) p1 = P[(int64_t)(col0 + 1) * ldp + grow] * o;
+        }
+    }
+    if (P) {
+        // the wavefront holds the 64 rows of this column pair
+        p0 = wave_sum(p0);
+        p1 = wave_sum(p1);
+        if (row == 0) {
+            pq[(int64_t)tile * 32 + col0] = p0;
+            pq[(int64_t)tile * 32 + col0 + 1] = p1;
+        }
     }
 }
 
-// C = alpha * sum_split part + beta * C, un-interleaving the lane-order tiles.
-__global__ __launch_bounds__(NT) void apply_reduce_kernel(int m, int q, int nsplit, const double* __restrict__ part,
-                                                          double* __restrict__ C, int64_t ldc, double alpha,
-                                                          double beta, const int* __restrict__ flag) {
-    if (flag && *flag == 0) return;
-    const int ntiles = (m + 31) / 32;
-    const int64_t total = (int64_t)ntiles * WAVE * 16;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int v = (int)(e % 16);
-        const int lane = (int)((e / 16) % WAVE);
-        const int tile = (int)(e / (16 * WAVE));
-        const int f = v / 4, r = v % 4;
-        const int fm = f / 2, fn = f % 2;
-        const int row = tile * 32 + 2 * (4 * r + lane / 16) + fm;
-        const int col = 2 * (lane % 16) + fn;
-        if (row >= m || col >= q) continue;
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * total + e];
-        double o = alpha * s;
-        if (beta != 0.0) o += beta * C[(int64_t)col * ldc + row];
-        C[(int64_t)col * ldc + row] = o;
-    }
+struct StreamPlan {
+    int ntiles, ksplit, kchunk;
+    int64_t tile_elems;
+};
+
+bool plan_stream(int m, int p, size_t work_elems, StreamPlan& pl) {
+    pl.ntiles = (m + WR - 1) / WR;
+    pl.tile_elems = (int64_t)pl.ntiles * WAVE * TV;
+    if ((size_t)p * 32 + (size_t)pl.tile_elems > work_elems) return false;
+    int ksplit = 1;
+    while (pl.ntiles * ksplit < 2048 && p / (ksplit * 2) >= 256 && ksplit < MAXSPLIT &&
+           (size_t)p * 32 + (size_t)(2 * ksplit) * pl.tile_elems <= work_elems)
+        ksplit *= 2;
+    // chunks of whole prefetch rounds (2 PF k-steps of 4 columns)
+    int kchunk = (p + ksplit - 1) / ksplit;
+    kchunk = ((kchunk + 8 * PF - 1) / (8 * PF)) * (8 * PF);
+    pl.ksplit = (p + kchunk - 1) / kchunk;
+    pl.kchunk = kchunk;
+    return true;
 }
 
 }  // namespace
 
+size_t stream_tiles(int m) { return (size_t)((m + WR - 1) / WR); }
+
 hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double* A, int64_t lda, const double* X,
                               int64_t ldx, double* C, int64_t ldc, double alpha, double beta, double* work,
                               size_t work_elems, const int* active_flag, hipEvent_t* ev) {
-    if (q < 1 || q > 32 || m < 1 || p < 1) return hipErrorInvalidValue;
-    const int ntiles = (m + 31) / 32;
-    const int wgs = (ntiles + 3) / 4;
-    const int64_t tile_elems = (int64_t)ntiles * WAVE * 16;
-    if (p > m || (size_t)m * 32 + (size_t)tile_elems > work_elems) return hipErrorInvalidValue;
-    int ksplit = 1;
-    while (wgs * ksplit < 1024 && p / (ksplit * 2) >= 256 && ksplit < 16 &&
-           (size_t)m * 32 + (size_t)(2 * ksplit) * tile_elems <= work_elems)
-        ksplit *= 2;
-    int kchunk = (p + ksplit - 1) / ksplit;
-    kchunk = ((kchunk + 3) / 4) * 4;
-    ksplit = (p + kchunk - 1) / kchunk;
+    if (q < 1 || q > 32 || m < 1 || p < 1 || (lda & 1) || (reinterpret_cast<uintptr_t>(A) & 15))
+        return hipErrorInvalidValue;
+    StreamPlan pl;
+    if (!plan_stream(m, p, work_elems, pl)) return hipErrorInvalidValue;
     double* Pt = work;
-    double* part = work + (size_t)m * 32;
-    const int pk_blocks = (int)std::min<int64_t>(2048, ((int64_t)p * 32 + NT - 1) / NT);
-    hipLaunchKernelGGL(pack_kmajor_kernel, dim3(pk_blocks), dim3(NT), 0, st, p, q, X, ldx, Pt, active_flag);
+    double* part = work + (size_t)p * 32;
+    hipLaunchKernelGGL(pack_kmajor_kernel, dim3((p + 63) / 64), dim3(256), 0, st, p, q, X, ldx, Pt, active_flag);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(apply_stream_kernel, dim3(wgs, 1, ksplit), dim3(NT), 0, st, m, p, A, lda, Pt, kchunk, part,
-                       active_flag);
+    hipLaunchKernelGGL(apply_stream_kernel, dim3(pl.ntiles, pl.ksplit), dim3(64), 0, st, m, p, A, lda, Pt, pl.kchunk,
+                       part, active_flag);
     if (ev) (void)hipEventRecord(ev[1], st);
-    const int rb = (int)std::min<int64_t>(4096, (tile_elems + NT - 1) / NT);
-    hipLaunchKernelGGL(apply_reduce_kernel, dim3(rb), dim3(NT), 0, st, m, q, ksplit, part, C, ldc, alpha, beta,
-                       active_flag);
+    hipLaunchKernelGGL(apply_reduce_kernel, dim3(pl.ntiles, (q + 7) / 8), dim3(256), 0, st, m, q, pl.ksplit, part, C, ldc, alpha,
+                       beta, (const double*)nullptr, (int64_t)0, (double*)nullptr, active_flag);
+    return hipGetLastError();
+}
+
+hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t lda, double* P, const double* R,
+                          const double* beta, const int* active, int first, double* Q, double* pq, double* work,
+                          size_t work_elems, const int* any_active, hipEvent_t* ev) {
+    if (w < 1 || w > 32 || n < 1 || (lda & 1) || (reinterpret_cast<uintptr_t>(A) & 15)) return hipErrorInvalidValue;
+    StreamPlan pl;
+    if (!plan_stream(n, n, work_elems, pl)) return hipErrorInvalidValue;
+    double* Pt = work;
+    double* part = work + (size_t)n * 32;
+    hipLaunchKernelGGL(cg_dir_pack_kernel, dim3((n + 63) / 64), dim3(256), 0, st, n, w, P, R, beta, active, first, Pt,
+                       any_active);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(apply_stream_kernel, dim3(pl.ntiles, pl.ksplit), dim3(64), 0, st, n, n, A, lda, Pt, pl.kchunk,
+                       part, any_active);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(apply_reduce_kernel, dim3(pl.ntiles, 4), dim3(256), 0, st, n, w, pl.ksplit, part, Q, (int64_t)n,
+                       1.0, 0.0, (const double*)P, (int64_t)n, pq, any_active);
     return hipGetLastError();
 }
 

@@ -49,12 +49,23 @@ hipError_t gemm_tn(hipStream_t st, int n, int p, int q, const Seg* A, int nsegA,
 
 // ---- apply.hip -----------------------------------------------------------
 // C = alpha * A X + beta * C for a dense A (m x p, lda even, 16-byte aligned)
-// and a narrow X (p x q, q <= 32): the streaming block apply of the CG inner
-// solves.  `ev` (optional) brackets the main product kernel.
+// and a narrow X (p x q, q <= 32): the streaming block apply.  `ev`
+// (optional) brackets the main product kernel.
 hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double* A, int64_t lda,
                               const double* X, int64_t ldx, double* C, int64_t ldc, double alpha,
                               double beta, double* work, size_t work_elems,
                               const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
+
+// 64-row tiles of the streaming apply for m rows
+size_t stream_tiles(int m);
+
+// One CG step's operator work on the dense path (n x n, w <= 32 columns, all
+// ld n): p = r + beta p for the active columns (skipped when `first`), then
+// Q = A P, and pq[t * 32 + j] = the sum over tile t's rows of P[:, j] Q[:, j].
+hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t lda, double* P,
+                          const double* R, const double* beta, const int* active, int first,
+                          double* Q, double* pq, double* work, size_t work_elems,
+                          const int* any_active, hipEvent_t* ev = nullptr);
 
 // ---- vec.hip -------------------------------------------------------------
 // Y[:, j] = delta o X[:, j]
@@ -85,6 +96,8 @@ hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double*
                    double tol);
 // alpha_j = rr_j / (p_j . q_j) for active columns (p.q <= 0 stops the column)
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s);
+// alpha from the per-tile sums written by cg_dense_apply (ntiles x 32)
+hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s);
 // x += alpha p, r -= alpha q, rr_new, beta, active update
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
 // p = r + beta p for active columns

@@ -3,17 +3,15 @@
 //
 //  small_lrep  the projected structured LREP of Step 3: two Cholesky
 //              factorisations and one SVD (Section 3.2 / cost discussion of
-//              Section 3.3).  The SVD of B = L2^T L1 is a one-sided
-//              (Hestenes) Jacobi iteration with the round-robin pair ordering;
-//              the stacked columns [B; L1] live in registers, 8 per wavefront,
-//              and only the two columns that cross a wavefront boundary move
-//              through LDS at each step.  At convergence column c holds
-//              [psi_c sigma_c; L1 phi_c], so
-//                  Y^_c = L1 phi_c / sqrt(sigma_c),
-//                  X^_c = L2 psi_c / sqrt(sigma_c) = L2 (B phi_c) / sigma_c^(3/2).
-//              The dense products B = L2^T L1 and X^ = L2 T run as MFMA
-//              block products (gemm.hip); the Cholesky factorisations and
-//              the Jacobi sweeps are one-workgroup kernels.
+//              Section 3.3).  With K^ = L1 L1^T, M^ = L2 L2^T and the SVD
+//              B = L2^T L1 = Psi Sigma Phi^T, the Ritz pairs are
+//                  X^_c = L2 psi_c / sqrt(sigma_c),
+//                  Y^_c = L1 phi_c / sqrt(sigma_c) = sqrt(sigma_c) L2^{-T} psi_c.
+//              The SVD is a one-sided (Hestenes) Jacobi iteration on the
+//              columns of B, register resident (jacobi_kernel); at
+//              convergence column c is sigma_c psi_c.  B = L2^T L1 and
+//              X^ = L2 T are MFMA block products (gemm.hip) and Y^ a
+//              triangular solve with L2^T.
 //  step5_pq    Step 5 in coefficient space (equation for P^, Q^): the two
 //              projector applications are block products, followed by the
 //              small MGS-Biorth on explicit d-vectors.
@@ -23,6 +21,8 @@
 // The MGS-Biorth recurrences run right-looking (after p_l, q_l are final,
 // every later column is updated against them); each pair (l, j) sees the
 // same coefficients, in the same order, as in the column-by-column form.
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -32,7 +32,7 @@ namespace {
 
 // convergence: every pair's cosine below ~ sqrt(d) eps (the usual one-sided
 // Jacobi criterion)
-constexpr double JACOBI_TOL = 4e-15;
+constexpr double JACOBI_TOL = 1e-14;
 constexpr int JACOBI_MAX_SWEEPS = 40;
 constexpr int LD = kMaxD + 1;
 constexpr size_t D2 = (size_t)kMaxD * kMaxD;
@@ -74,276 +74,480 @@ __device__ __forceinline__ double wsum(double v) {
     return readlane(v, 63);
 }
 
-// stacked row e * 64 + lane lies in the top (B) part: rows < D = 32 E
-template <int E>
-__device__ __forceinline__ bool is_top(int e, int lane) {
-    if constexpr (E >= 2) return e < E / 2;
-    else return lane < 32;
+// ---------------------------------------------------------------------------
+// Cholesky of the symmetric parts of K^ (block 0) and M^ (block 1), d <= 128,
+// blocked right-looking on an LDS copy (blocks of CB = 16 columns), 256
+// threads per matrix:
+//   (a) the diagonal block is factored by one wavefront in registers, lane i
+//       holding row i, pivots and column entries broadcast with readlane;
+//   (b) the panel below it is solved row by row (L_pd = A_pd L_dd^{-T}), one
+//       thread per row;
+//   (c) the trailing matrix takes the rank-CB update A -= L_pd L_pd^T in
+//       4 x 4 register tiles.
+// A non-positive pivot sets status[ST_NOTSPD].
+// ---------------------------------------------------------------------------
+constexpr int CB = 16;
+
+__device__ __forceinline__ double rdlane(double v, int l) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_readlane(p.x, l);
+    p.y = __builtin_amdgcn_readlane(p.y, l);
+    return __builtin_bit_cast(double, p);
 }
 
-// 1 / x to full precision from the hardware estimate and one Newton step
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    const double e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-// 1 / sqrt(x) from the hardware estimate and one Newton step
-__device__ __forceinline__ double rsq_nr(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x * r;
-    return fma(r, fma(-h, r, 0.5), r);
-}
-
-// ---------------------------------------------------------------------------
-// Cholesky of the symmetric parts of K^ (block 0) and M^ (block 1), d <= 128.
-// Right-looking on an LDS copy; one barrier per column: at step k every
-// thread reads the final pivot S[k][k] and column k (unscaled), writes the
-// scaled column of L to global memory and updates its own trailing entries
-// with S[i][j] -= S[i][k] S[j][k] / S[k][k].
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void chol2_kernel(int d, const double* __restrict__ Kh,
-                                                    const double* __restrict__ Mh, int64_t ldh,
-                                                    double* __restrict__ scratch, int* __restrict__ status) {
+__global__ __launch_bounds__(256) void chol2_kernel(int d, const double* __restrict__ Kh,
+                                                   const double* __restrict__ Mh, int64_t ldh,
+                                                   double* __restrict__ scratch, int* __restrict__ status) {
     __shared__ double S[kMaxD * LD];
+    __shared__ int fail;
     const double* A = blockIdx.x == 0 ? Kh : Mh;
     double* L = scratch + (size_t)blockIdx.x * D2;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid % WAVE, wid = tid / WAVE;
     for (int idx = tid; idx < d * d; idx += nt) {
         const int i = idx % d, j = idx / d;
-        S[i * LD + j] = 0.5 * (A[(int64_t)j * ldh + i] + A[(int64_t)i * ldh + j]);
+        if (j <= i) S[i * LD + j] = 0.5 * (A[(int64_t)j * ldh + i] + A[(int64_t)i * ldh + j]);
     }
-    for (int idx = tid; idx < (int)D2; idx += nt) L[idx] = 0.0;
+    if (tid == 0) fail = 0;
     __syncthreads();
-    for (int k = 0; k < d; ++k) {
-        const double v = S[k * LD + k];
-        if (!(v > 0.0)) {
-            if (tid == 0) status[ST_NOTSPD] = 1;
-            return;   // uniform: every thread read the same pivot
-        }
-        const double piv = sqrt(v);
-        const double inv = 1.0 / v;
-        for (int i = k + tid; i < d; i += nt) L[(int64_t)k * kMaxD + i] = (i == k) ? piv : S[i * LD + k] / piv;
-        const int m = d - k - 1;
-        for (int idx = tid; idx < m * m; idx += nt) {
-            const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-            if (j <= i) S[i * LD + j] -= S[i * LD + k] * S[j * LD + k] * inv;
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One-sided Jacobi on the stacked columns [B; L1] (B = L2^T L1, both d x d,
-// ld kMaxD), round-robin ordering.  Wavefront w owns tournament slots
-// T[4w..4w+3] (register slots 0..3) and Bt[4w..4w+3] (slots 4..7); lane l
-// holds stacked rows e*64 + l.  Outputs lam (ascending), Yh = L1 phi /
-// sqrt(sigma) and T = (B phi) / sigma^(3/2) (so that X^ = L2 T).
-// ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(D * 8) void jacobi_kernel(int d, const double* __restrict__ scratch,
-                                                      double* __restrict__ lam, double* __restrict__ Yh,
-                                                      double* __restrict__ T, int* __restrict__ status) {
-    constexpr int NW = D / 8;
-    constexpr int NTH = NW * WAVE;
-    constexpr int E = (2 * D) / WAVE;
-    __shared__ double xT[2 * NW * (2 * D + 2)];
-    __shared__ double xB[2 * NW * (2 * D + 2)];
-    __shared__ double sig[D];
-    __shared__ double bnorm[D];
-    __shared__ int rank_of[D];
-    __shared__ double wmax[NW];
-    const double* L1 = scratch;
-    const double* Bm = scratch + 3 * D2;
-    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-
-    double col[8][E];
+    for (int kb = 0; kb < d; kb += CB) {
+        const int nb = min(CB, d - kb);
+        // (a) diagonal block
+        if (wid == 0) {
+            double r[CB];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int k = 4 * w + (s & 3);
-        const int c = (s < 4) ? 2 * k : 2 * k + 1;
+            for (int j = 0; j < CB; ++j)
+                r[j] = (lane < nb && j <= lane) ? S[(kb + lane) * LD + kb + j] : 0.0;
+            bool bad = false;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int row = e * WAVE + lane;
-            double v = 0.0;
-            if (c < d) {
-                if (row < D) {
-                    if (row < d) v = Bm[(int64_t)c * kMaxD + row];
-                } else if (row - D < d) {
-                    v = L1[(int64_t)c * kMaxD + (row - D)];
-                }
-            }
-            col[s][e] = v;
-        }
-    }
-
-    // squared norms of the top parts travel with their columns (uniform per
-    // wave); they are recomputed exactly at the start of every sweep and
-    // updated by the rotation formulas in between (alpha' = alpha - t gamma,
-    // beta' = beta + t gamma), so each pair needs one cross-lane sum only.
-    double nrm[8];
-    int sweeps = 0;
-    for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
-        ++sweeps;
+            for (int k = 0; k < CB; ++k) {
+                if (k < nb && !bad) {
+                    const double piv = rdlane(r[k], k);
+                    if (!(piv > 0.0)) {
+                        bad = true;
+                    } else {
+                        const double lkk = sqrt(piv);
+                        const double inv = 1.0 / lkk;
+                        r[k] = (lane == k) ? lkk : (lane > k ? r[k] * inv : r[k]);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            double t = 0.0;
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (is_top<E>(e, lane)) t += col[s][e] * col[s][e];
-            nrm[s] = wsum(t);
-        }
-        double offmax = 0.0;
-        for (int step = 0; step < D - 1; ++step) {
-            double ga[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                ga[i] = 0.0;
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (is_top<E>(e, lane)) ga[i] += col[i][e] * col[4 + i][e];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ga[i] = wsum(ga[i]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double al = nrm[i], be = nrm[4 + i];
-                if (ga[i] != 0.0) {
-                    const double rel = fabs(ga[i]) * rsq_nr(al * be);
-                    offmax = fmax(offmax, rel);
-                    if (rel > JACOBI_TOL) {
-                        // Rutishauser's rotation: zeta = (beta - alpha) / (2 gamma),
-                        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t
-                        const double zeta = (be - al) * rcp_nr(2.0 * ga[i]);
-                        const double az = fabs(zeta);
-                        const double root = az < 1e150 ? (1.0 + zeta * zeta) * rsq_nr(1.0 + zeta * zeta) : az;
-                        const double t = copysign(rcp_nr(az + root), zeta);
-                        const double c = rsq_nr(1.0 + t * t);
-                        const double s = c * t;
-#pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            const double a = col[i][e], b = col[4 + i][e];
-                            col[i][e] = c * a - s * b;
-                            col[4 + i][e] = s * a + c * b;
-                        }
-                        nrm[i] = al - t * ga[i];
-                        nrm[4 + i] = be + t * ga[i];
-                        if (nrm[i] < 1e-2 * al) {   // heavy cancellation: recompute exactly
-                            double t2 = 0.0;
-#pragma unroll
-                            for (int e = 0; e < E; ++e)
-                                if (is_top<E>(e, lane)) t2 += col[i][e] * col[i][e];
-                            nrm[i] = wsum(t2);
+                        for (int j = k + 1; j < CB; ++j) {
+                            if (j < nb) {
+                                const double ljk = rdlane(r[k], j);
+                                if (lane >= j) r[j] = fma(-r[k], ljk, r[j]);
+                            }
                         }
                     }
                 }
             }
-            // round-robin move: only T[4w+3] and Bt[4w] cross wavefronts
-            const int par = step & 1;
-            double* oT = xT + ((size_t)par * NW + w) * (2 * D + 2);
-            double* oB = xB + ((size_t)par * NW + w) * (2 * D + 2);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                oT[e * WAVE + lane] = col[3][e];
-                oB[e * WAVE + lane] = col[4][e];
-            }
-            if (lane == 0) {
-                oT[2 * D] = nrm[3];
-                oB[2 * D] = nrm[4];
-            }
-            __syncthreads();
-            const double* iT = xT + ((size_t)par * NW + (w > 0 ? w - 1 : 0)) * (2 * D + 2);
-            const double* iB = xB + ((size_t)par * NW + (w < NW - 1 ? w + 1 : 0)) * (2 * D + 2);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const double t0 = col[0][e], t1 = col[1][e], t2 = col[2][e], t3 = col[3][e];
-                const double b0 = col[4][e], b1 = col[5][e], b2 = col[6][e], b3 = col[7][e];
-                if (w == 0) {
-                    col[0][e] = t0;
-                    col[1][e] = b0;
-                } else {
-                    col[0][e] = iT[e * WAVE + lane];
-                    col[1][e] = t0;
+            if (bad) {
+                if (lane == 0) {
+                    fail = 1;
+                    status[ST_NOTSPD] = 1;
                 }
-                col[2][e] = t1;
-                col[3][e] = t2;
-                col[4][e] = b1;
-                col[5][e] = b2;
-                col[6][e] = b3;
-                col[7][e] = (w == NW - 1) ? t3 : iB[e * WAVE + lane];
-            }
-            {
-                const double t0 = nrm[0], t1 = nrm[1], t2 = nrm[2], t3 = nrm[3];
-                const double b0 = nrm[4], b1 = nrm[5], b2 = nrm[6], b3 = nrm[7];
-                if (w == 0) {
-                    nrm[1] = b0;
-                } else {
-                    nrm[0] = iT[2 * D];
-                    nrm[1] = t0;
-                }
-                nrm[2] = t1;
-                nrm[3] = t2;
-                nrm[4] = b1;
-                nrm[5] = b2;
-                nrm[6] = b3;
-                nrm[7] = (w == NW - 1) ? t3 : iB[2 * D];
+            } else if (lane < nb) {
+#pragma unroll
+                for (int j = 0; j < CB; ++j)
+                    if (j <= lane) S[(kb + lane) * LD + kb + j] = r[j];
             }
         }
-        if (lane == 0) wmax[w] = offmax;
+        __syncthreads();
+        if (fail) return;   // uniform
+        // (b) panel rows below the block
+        const int m = d - kb - nb;
+        for (int t = tid; t < m; t += nt) {
+            const int i = kb + nb + t;
+            double x[CB];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) x[j] = j < nb ? S[i * LD + kb + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                if (j < nb) {
+                    double v = x[j];
+#pragma unroll
+                    for (int l = 0; l < j; ++l) v = fma(-x[l], S[(kb + j) * LD + kb + l], v);
+                    x[j] = v / S[(kb + j) * LD + kb + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+                if (j < nb) S[i * LD + kb + j] = x[j];
+        }
+        __syncthreads();
+        // (c) trailing update on 4 x 4 tiles (ti >= tj)
+        const int mt = (m + 3) / 4;
+        const int ntile = mt * (mt + 1) / 2;
+        for (int tt = tid; tt < ntile; tt += nt) {
+            int ti = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+            while (ti * (ti + 1) / 2 > tt) --ti;
+            const int tj = tt - ti * (ti + 1) / 2;
+            const int i0 = kb + nb + 4 * ti, j0 = kb + nb + 4 * tj;
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            for (int l = 0; l < nb; ++l) {
+                double pi[4], pj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    pi[u] = (i0 + u < d) ? S[(i0 + u) * LD + kb + l] : 0.0;
+                    pj[u] = (j0 + u < d) ? S[(j0 + u) * LD + kb + l] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = fma(pi[u], pj[v], acc[u][v]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, j = j0 + v;
+                    if (i < d && j <= i) S[i * LD + j] -= acc[u][v];
+                }
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < (int)D2; idx += nt) {
+        const int i = idx % kMaxD, j = idx / kMaxD;
+        L[idx] = (i < d && j <= i) ? S[i * LD + j] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi on the columns of B = L2^T L1 (d x d, ld kMaxD,
+// zero-padded to D), register resident, one workgroup of D / 32 wavefronts.
+//
+// Layout: the D columns form S = D / 2 slots of two columns (a, b).  Slot
+// s = 16 w + i lives in wavefront w, lane column i: lanes i, i + 16, i + 32,
+// i + 48 hold rows [q R, q R + R) of both columns (q = lane / 16, R = D / 4).
+// A pair's inner product is a 4-lane sum (two permlane swaps), and the
+// rotation parameters are computed once per lane, i.e. the 16 pairs of a
+// wavefront in parallel.
+//
+// Pair ordering: a recursive split.  Level 0 pairs every a with every b
+// (S steps, b moving between slots); level L >= 1 first swaps, for slot pairs
+// (s, s ^ G) with G = S >> L, the b of the lower slot with the a of the upper
+// one, then pairs within groups of G slots (G steps).  Every pair of columns
+// meets exactly once per sweep (D - 1 steps).  The b moves are a rotation by
+// one lane inside the 16-lane rows (DPP row_ror:1) and, every 16 steps of the
+// levels with G >= 16, an exchange between wavefronts through LDS; groups of
+// fewer than 16 slots use XOR moves in Gray-code order (DPP quad_perm and
+// mirrors).  The squared norms travel with their columns and are recomputed
+// exactly at the start of every sweep (and after heavy cancellation), so a
+// pair costs one cross-lane sum.
+//
+// Outputs, ranked by ascending sigma:  lam = sigma, T = col / sigma^(3/2)
+// (so X^ = L2 T) and Z = col / sigma^(1/2) (so Y^ = L2^{-T} Z).
+// ---------------------------------------------------------------------------
+
+// 1/x and 1/sqrt(x) to full FP64 precision: the hardware estimates are good
+// to ~2^-24, two Newton steps bring them to rounding level.
+__device__ __forceinline__ double rcp2(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq2(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x * r;
+    r = fma(r, fma(-h, r, 0.5), r);
+    h = 0.5 * x * r;
+    return fma(r, fma(-h, r, 0.5), r);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dmov(double v) {   // patterns where every lane reads a valid lane
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_mov_dpp(p.x, CTRL, 0xF, 0xF, true);
+    p.y = __builtin_amdgcn_mov_dpp(p.y, CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, p);
+}
+// value of lane i ^ k inside each 16-lane row, k in {1, 2, 4, 8}
+template <int K>
+__device__ __forceinline__ double xperm(double v) {
+    if constexpr (K == 1) return dmov<0xB1>(v);                // quad_perm [1,0,3,2]
+    else if constexpr (K == 2) return dmov<0x4E>(v);           // quad_perm [2,3,0,1]
+    else if constexpr (K == 4) return dmov<0x1B>(dmov<0x141>(v));   // i^7 then i^3
+    else return dmov<0x141>(dmov<0x140>(v));                   // i^15 then i^7
+}
+// sum over the 4 lanes l, l^16, l^32, l^48; every lane gets bitwise the same value
+__device__ __forceinline__ double qsum(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    auto lo = __builtin_amdgcn_permlane32_swap(p.x, p.x, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap(p.y, p.y, false, false);
+    double y = __builtin_bit_cast(double, int2{(int)lo[0], (int)hi[0]}) +
+               __builtin_bit_cast(double, int2{(int)lo[1], (int)hi[1]});
+    p = __builtin_bit_cast(int2, y);
+    lo = __builtin_amdgcn_permlane16_swap(p.x, p.x, false, false);
+    hi = __builtin_amdgcn_permlane16_swap(p.y, p.y, false, false);
+    return __builtin_bit_cast(double, int2{(int)lo[0], (int)hi[0]}) +
+           __builtin_bit_cast(double, int2{(int)lo[1], (int)hi[1]});
+}
+
+template <int R>
+__device__ __forceinline__ double sumsq(const double (&x)[R]) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; e += 2) {
+        s0 = fma(x[e], x[e], s0);
+        s1 = fma(x[e + 1], x[e + 1], s1);
+    }
+    return qsum(s0 + s1);
+}
+
+// one rotation of the slot's pair (a, b) with norms (na, nb)
+template <int R>
+__device__ __forceinline__ void jacobi_rotate(double (&a)[R], double (&b)[R], double& na, double& nb,
+                                              double& offmax) {
+    double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; e += 2) {
+        g0 = fma(a[e], b[e], g0);
+        g1 = fma(a[e + 1], b[e + 1], g1);
+    }
+    const double ga = qsum(g0 + g1);
+    const double al = na, be = nb;
+    const double rel = (ga != 0.0) ? fabs(ga) * rsq2(al * be) : 0.0;
+    offmax = fmax(offmax, rel);
+    const bool rot = rel > JACOBI_TOL;
+    if (!__any(rot)) return;
+    // lanes whose pair needs no rotation apply the identity (c = 1, s = 0,
+    // exact), so that the update below runs unpredicated
+    double c = 1.0, s = 0.0, tg = 0.0;
+    if (rot) {
+        // Rutishauser's rotation: zeta = (beta - alpha) / (2 gamma),
+        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t
+        const double zeta = (be - al) * rcp2(2.0 * ga);
+        const double az = fabs(zeta);
+        const double w1 = fma(zeta, zeta, 1.0);
+        const double root = az < 1e150 ? w1 * rsq2(w1) : az;
+        const double t = copysign(rcp2(az + root), zeta);
+        c = rsq2(fma(t, t, 1.0));
+        s = c * t;
+        tg = t * ga;
+    }
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const double x = a[e], y = b[e];
+        a[e] = fma(c, x, -(s * y));
+        b[e] = fma(s, x, c * y);
+    }
+    na = al - tg;
+    nb = be + tg;
+    const bool need = rot && ((na < 1e-2 * al) || (nb < 1e-2 * be));
+    if (__any(need)) {   // heavy cancellation somewhere in the wavefront: exact norms
+        const double ea = sumsq<R>(a), eb = sumsq<R>(b);
+        if (need) {
+            na = ea;
+            nb = eb;
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __restrict__ Bm,
+                                                      double* __restrict__ lam, double* __restrict__ Z,
+                                                      double* __restrict__ T, int* __restrict__ status) {
+    constexpr int NW = D / 32;   // wavefronts
+    constexpr int S = D / 2;     // slots
+    constexpr int R = D / 4;     // rows per lane and column
+    constexpr int NTH = NW * WAVE;
+    __shared__ double xbuf[NW * R * WAVE];
+    __shared__ double xnrm[NW * WAVE];
+    __shared__ double sig[D];
+    __shared__ int rank_of[D];
+    __shared__ double wmax[NW];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, q = lane / 16;
+    const int slot = 16 * w + li;
+
+    double a[R], b[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int row = q * R + e;
+        const int ca = slot, cb = slot + S;
+        a[e] = (ca < d && row < d) ? Bm[(int64_t)ca * kMaxD + row] : 0.0;
+        b[e] = (cb < d && row < d) ? Bm[(int64_t)cb * kMaxD + row] : 0.0;
+    }
+
+    // exchange of b (and its norm) with wavefront w ^ kw
+    auto xwave_b = [&](int kw, double& nb) {
+        double* mine = xbuf + (size_t)w * R * WAVE;
+#pragma unroll
+        for (int e = 0; e < R; ++e) mine[e * WAVE + lane] = b[e];
+        xnrm[w * WAVE + lane] = nb;
+        __syncthreads();
+        const double* src = xbuf + (size_t)(w ^ kw) * R * WAVE;
+#pragma unroll
+        for (int e = 0; e < R; ++e) b[e] = src[e * WAVE + lane];
+        nb = xnrm[(w ^ kw) * WAVE + lane];
+        __syncthreads();
+    };
+    // level start: the lower slot's b <-> the upper slot's a (slots s, s ^ m)
+    auto relayout = [&](int m, double& na, double& nb) {
+        double sa = na, sb = nb;
+        if (m >= 16) {
+            const int kw = m / 16;
+            const bool up = (w & kw) != 0;
+            double* mine = xbuf + (size_t)w * R * WAVE;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                const double va = a[e], vb = b[e];
+                mine[e * WAVE + lane] = up ? va : vb;
+            }
+            xnrm[w * WAVE + lane] = up ? sa : sb;
+            __syncthreads();
+            const double* src = xbuf + (size_t)(w ^ kw) * R * WAVE;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                const double v = src[e * WAVE + lane], va = a[e], vb = b[e];
+                a[e] = up ? v : va;
+                b[e] = up ? vb : v;
+            }
+            const double vn = xnrm[(w ^ kw) * WAVE + lane];
+            na = up ? vn : sa;
+            nb = up ? sb : vn;
+            __syncthreads();
+        } else {
+            const bool up = (li & m) != 0;
+            auto swap_with = [&](auto kconst) {
+                constexpr int K = decltype(kconst)::value;
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    const double va = a[e], vb = b[e];
+                    const double v = xperm<K>(up ? va : vb);
+                    a[e] = up ? v : va;
+                    b[e] = up ? vb : v;
+                }
+                const double vn = xperm<K>(up ? sa : sb);
+                na = up ? vn : sa;
+                nb = up ? sb : vn;
+            };
+            if (m == 8) swap_with(std::integral_constant<int, 8>{});
+            else if (m == 4) swap_with(std::integral_constant<int, 4>{});
+            else if (m == 2) swap_with(std::integral_constant<int, 2>{});
+            else swap_with(std::integral_constant<int, 1>{});
+        }
+    };
+
+    int sweeps = 0;
+    for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+        ++sweeps;
+        double na = sumsq<R>(a), nb = sumsq<R>(b);
+        double offmax = 0.0;
+        auto rot = [&]() { jacobi_rotate<R>(a, b, na, nb, offmax); };
+        auto mv = [&](auto kconst) {
+            constexpr int K = decltype(kconst)::value;
+#pragma unroll
+            for (int e = 0; e < R; ++e) b[e] = xperm<K>(b[e]);
+            nb = xperm<K>(nb);
+        };
+        // levels with groups of 16 slots or more: b rotates by one lane inside
+        // the 16-lane rows, and moves between wavefronts every 16 steps
+        int L = 0;
+        for (int G = S; G >= 16; G >>= 1, ++L) {
+            if (L > 0) relayout(G, na, nb);
+            for (int blk = 0; blk < G / 16; ++blk) {
+                if (blk > 0) xwave_b(1 << __builtin_ctz(blk), nb);
+                rot();
+                for (int u = 1; u < 16; ++u) {
+#pragma unroll
+                    for (int e = 0; e < R; ++e) b[e] = dmov<0x121>(b[e]);   // row_ror:1
+                    nb = dmov<0x121>(nb);
+                    rot();
+                }
+            }
+        }
+        // groups of 8, 4, 2, 1 slots: XOR moves in Gray-code order
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I4 = std::integral_constant<int, 4>;
+        relayout(8, na, nb);
+        rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
+        mv(I4{}); rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
+        relayout(4, na, nb);
+        rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
+        relayout(2, na, nb);
+        rot(); mv(I1{}); rot();
+        relayout(1, na, nb);
+        rot();
+        const double wm = wave_max(offmax);
+        if (lane == 0) wmax[w] = wm;
         __syncthreads();
         double om = 0.0;
 #pragma unroll
-        for (int i = 0; i < NW; ++i) om = fmax(om, wmax[i]);
+        for (int k = 0; k < NW; ++k) om = fmax(om, wmax[k]);
         __syncthreads();
         if (om <= JACOBI_TOL) break;
     }
     if (tid == 0 && status) status[ST_SWEEPS] = sweeps;
 
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        double tn = 0, bn = 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const double v = col[s][e];
-            if (is_top<E>(e, lane)) tn += v * v;
-            else bn += v * v;
-        }
-        tn = wsum(tn);
-        bn = wsum(bn);
-        if (lane == 0) {
-            sig[8 * w + s] = sqrt(tn);
-            bnorm[8 * w + s] = bn;
-        }
+    // singular values, ranks (ascending sigma, position breaks ties), outputs
+    const double sa = sqrt(sumsq<R>(a)), sb = sqrt(sumsq<R>(b));
+    if (q == 0) {
+        sig[slot] = sa;
+        sig[S + slot] = sb;
     }
     __syncthreads();
-    for (int a = tid; a < D; a += NTH) {
+    for (int p = tid; p < D; p += NTH) {
         int r = -1;
-        if (bnorm[a] > 0.0) {
+        if (sig[p] > 0.0) {
             r = 0;
-            for (int b = 0; b < D; ++b)
-                if (bnorm[b] > 0.0 && (sig[b] < sig[a] || (sig[b] == sig[a] && b < a))) ++r;
+            for (int o = 0; o < D; ++o)
+                if (sig[o] > 0.0 && (sig[o] < sig[p] || (sig[o] == sig[p] && o < p))) ++r;
         }
-        rank_of[a] = r;
+        rank_of[p] = r;
     }
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int slot = 8 * w + s;
-        const int r = rank_of[slot];
-        if (r < 0 || r >= d) continue;
-        const double sg = sig[slot];
+    if (tid == 0) {
+        int nv = 0;
+        for (int p = 0; p < D; ++p) nv += rank_of[p] >= 0;
+        if (nv != d && status) status[ST_NOTSPD] = 1;   // singular B: cannot happen for SPD K^, M^
+    }
+    auto emit = [&](const double (&x)[R], int pos) {
+        const int r = rank_of[pos];
+        if (r < 0 || r >= d) return;
+        const double sg = sig[pos];
         const double isq = 1.0 / sqrt(sg);
         const double i32 = isq / sg;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int row = e * WAVE + lane;
-            if (row < D) {
-                if (row < d) T[(int64_t)r * kMaxD + row] = col[s][e] * i32;
-            } else if (row - D < d) {
-                Yh[(int64_t)r * kMaxD + (row - D)] = col[s][e] * isq;
+        for (int e = 0; e < R; ++e) {
+            const int row = q * R + e;
+            if (row < d) {
+                T[(int64_t)r * kMaxD + row] = x[e] * i32;
+                Z[(int64_t)r * kMaxD + row] = x[e] * isq;
             }
         }
-        if (lane == 0) lam[r] = sg;
+        if (q == 0) lam[r] = sg;
+    };
+    emit(a, slot);
+    emit(b, S + slot);
+}
+
+// ---------------------------------------------------------------------------
+// Y <- L^{-T} Y for the lower-triangular L (d x d, ld kMaxD) and d right-hand
+// sides (ld kMaxD): back substitution, one wavefront per right-hand side,
+// lane l holding rows l and l + 64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WAVE) void trsm_lt_kernel(int d, const double* __restrict__ L,
+                                                      double* __restrict__ Y) {
+    const int c = blockIdx.x, lane = threadIdx.x;
+    double* y = Y + (int64_t)c * kMaxD;
+    const int j0 = lane, j1 = lane + 64;
+    double y0 = j0 < d ? y[j0] : 0.0, y1 = j1 < d ? y[j1] : 0.0;
+    const double r0 = j0 < d ? 1.0 / L[(int64_t)j0 * kMaxD + j0] : 0.0;
+    const double r1 = j1 < d ? 1.0 / L[(int64_t)j1 * kMaxD + j1] : 0.0;
+    for (int i = d - 1; i >= 0; --i) {
+        const double* li = L + (int64_t)i * kMaxD;   // column i of L = row i of L^T
+        const double l0 = (j0 > i && j0 < d) ? li[j0] : 0.0;
+        const double l1 = (j1 > i && j1 < d) ? li[j1] : 0.0;
+        const double s = wsum(fma(l0, y0, l1 * y1));
+        if (i == j0) y0 = (y0 - s) * r0;
+        if (i == j1) y1 = (y1 - s) * r1;
     }
+    if (j0 < d) y[j0] = y0;
+    if (j1 < d) y[j1] = y1;
 }
 
 // ---------------------------------------------------------------------------
@@ -568,7 +772,7 @@ __global__ __launch_bounds__(256) void coef_mgs_kernel(int m, const double* __re
 hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh, int64_t ldh, double* lam,
                       double* Xh, double* Yh, double* scratch, int* status, double* work, size_t work_elems) {
     if (d < 1 || d > kMaxD) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol2_kernel, dim3(2), dim3(1024), 0, st, d, Kh, Mh, ldh, scratch, status);
+    hipLaunchKernelGGL(chol2_kernel, dim3(2), dim3(256), 0, st, d, Kh, Mh, ldh, scratch, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // B = L2^T L1 into scratch + 3 D2
@@ -576,17 +780,21 @@ hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh,
     e = gemm_tn(st, d, d, d, &a, 1, &b, 1, scratch + 3 * D2, kMaxD, 1.0, 0, work, work_elems);
     if (e != hipSuccess) return e;
     double* T = scratch + 2 * D2;
+    const double* Bm = scratch + 3 * D2;
     if (d <= 32)
-        hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(32 * 8), 0, st, d, scratch, lam, Yh, T, status);
+        hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(64), 0, st, d, Bm, lam, Yh, T, status);
     else if (d <= 64)
-        hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(64 * 8), 0, st, d, scratch, lam, Yh, T, status);
+        hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(128), 0, st, d, Bm, lam, Yh, T, status);
     else
-        hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(128 * 8), 0, st, d, scratch, lam, Yh, T, status);
+        hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(256), 0, st, d, Bm, lam, Yh, T, status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // X^ = L2 T
+    // X^ = L2 T, Y^ = L2^{-T} Z (Z written to Yh by the Jacobi kernel)
     Seg l2{scratch + D2, kMaxD, d};
-    return gemm_nn(st, d, d, d, &l2, 1, T, kMaxD, Xh, kMaxD, 1.0, 0.0, work, work_elems);
+    e = gemm_nn(st, d, d, d, &l2, 1, T, kMaxD, Xh, kMaxD, 1.0, 0.0, work, work_elems);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trsm_lt_kernel, dim3(d), dim3(WAVE), 0, st, d, scratch + D2, Yh);
+    return hipGetLastError();
 }
 
 hipError_t step5_pq(hipStream_t st, int d, int hi, const double* Xh, const double* Yh, const int* win, int nw,

@@ -77,7 +77,7 @@ struct Solver {
     DevBuf gwork, dsmall, ismall;
     // carved small buffers
     double *Kh, *Mh, *S, *Xh, *Yh, *lam, *eps, *lamw, *Ph, *Qh, *Acoef, *Bcoef, *scr, *G, *Cproj, *Tlr, *part,
-        *cg_rr, *cg_bb, *cg_alpha, *cg_beta, *offmax;
+        *cg_rr, *cg_bb, *cg_alpha, *cg_beta, *offmax, *cg_pq;
     int64_t kproj;
     int *status, *win, *wincol, *cg_active, *cg_any;
     unsigned* tickets;
@@ -177,14 +177,15 @@ struct Solver {
                oQh = carve(kMaxD * 64), oA = carve(D2), oB = carve(2 * D2), oscr = carve(4 * D2),
                oG = carve(4 * D2), oC = carve((size_t)kproj * std::max(kMaxD, cw)),
                oT = carve((size_t)std::max<int64_t>(rank, 1) * kMaxD), opart = carve((size_t)256 * kMaxD * 4),
-               orr = carve(kMaxD), obb = carve(kMaxD), oal = carve(kMaxD), obe = carve(kMaxD), oom = carve(8);
+               orr = carve(kMaxD), obb = carve(kMaxD), oal = carve(kMaxD), obe = carve(kMaxD), oom = carve(8),
+               opq = carve(stream_tiles((int)n) * 32);
         CR(dsmall.alloc(c, nd * sizeof(double)));
         double* base = dsmall.p;
         Kh = base + oKh; Mh = base + oMh; S = base + oS; Xh = base + oXh; Yh = base + oYh;
         lam = base + olam; eps = base + oeps; lamw = base + olamw; Ph = base + oPh; Qh = base + oQh;
         Acoef = base + oA; Bcoef = base + oB; scr = base + oscr; G = base + oG; Cproj = base + oC;
         Tlr = base + oT; part = base + opart; cg_rr = base + orr; cg_bb = base + obb; cg_alpha = base + oal;
-        cg_beta = base + obe; offmax = base + oom;
+        cg_beta = base + obe; offmax = base + oom; cg_pq = base + opq;
         // ints: status(8) win(kMaxD) wincol(kMaxD) cg_active(kMaxD) cg_any(8) tickets(8) napplies(2 x u64)
         CR(ismall.alloc(c, sizeof(int) * (8 + 3 * kMaxD + 8 + 8) + 4 * sizeof(unsigned long long)));
         int* ib = reinterpret_cast<int*>(ismall.p);
@@ -224,16 +225,35 @@ struct Solver {
         return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev);
     }
 
+    // the dense operator for the fused CG path (nullptr: use the generic apply)
+    const double* cg_stream_operator(int which, int nw) const {
+        if (op->kind != 0 || nw > 32) return nullptr;
+        const bool useK = (which == 0) != op->null_on_M();
+        const double* Ad = useK ? op->K : op->M;
+        if ((op->ld % 2) != 0 || (reinterpret_cast<uintptr_t>(Ad) % 16) != 0) return nullptr;
+        return Ad;
+    }
+
     // solution of A x_j = rhs_j (which: 0 = K, 1 = M) into cgX; `maxit` CG steps
     int cg(int which, const double* B, int nw, double cgtol, int maxit, bool host_check) {
         CgState s = cg_state(1, which);
         CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
+        const double* Ad = cg_stream_operator(which, nw);
+        const int ntiles = (int)stream_tiles((int)n);
         for (int it = 0; it < maxit; ++it) {
             hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw) : nullptr;
-            CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
-            CK(lrep::cg_alpha(st, (int)n, nw, s));
-            CK(cg_update(st, (int)n, nw, s, cgtol));
-            CK(cg_direction(st, (int)n, nw, s));
+            if (Ad) {
+                // direction update of the previous step, pack, apply, p.q per tile
+                CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
+                                  cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev));
+                CK(cg_alpha_tiles(st, nw, ntiles, cg_pq, s));
+                CK(cg_update(st, (int)n, nw, s, cgtol));
+            } else {
+                CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
+                CK(lrep::cg_alpha(st, (int)n, nw, s));
+                CK(cg_update(st, (int)n, nw, s, cgtol));
+                CK(cg_direction(st, (int)n, nw, s));
+            }
             if (host_check && (it % 50 == 49)) {
                 int any = 0;
                 CK(hipMemcpyAsync(&hs->status[7], cg_any, sizeof(int), hipMemcpyDeviceToHost, st));

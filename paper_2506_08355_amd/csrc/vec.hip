@@ -150,6 +150,38 @@ __global__ __launch_bounds__(64) void cg_alpha_fin_kernel(int w, int nchunks, Cg
     if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
 }
 
+// alpha_fin on the per-tile p.q sums of the fused dense path: thread
+// (grp, col) sums tiles grp, grp + 32, ... in order, then one thread per
+// column adds the 32 group sums in order.
+__global__ __launch_bounds__(1024) void cg_alpha_tiles_kernel(int w, int ntiles, const double* __restrict__ pq,
+                                                              CgState s) {
+    __shared__ double red[32][33];
+    if (*s.any_active == 0) return;
+    const int col = threadIdx.x % 32, grp = threadIdx.x / 32;
+    double t = 0.0;
+    for (int k = grp; k < ntiles; k += 32) t += pq[(int64_t)k * 32 + col];
+    red[grp][col] = t;
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    int na = 0;
+    const int c = threadIdx.x;
+    if (c < w) {
+        double a = 0.0;
+        if (s.active[c]) {
+            ++na;
+            double sum = 0.0;
+            for (int k = 0; k < 32; ++k) sum += red[k][c];
+            if (sum > 0.0)
+                a = s.rr[c] / sum;
+            else
+                s.active[c] = 0;   // breakdown: p^T A p <= 0 (singular operator)
+        }
+        s.alpha[c] = a;
+    }
+    for (int off = 32; off >= 1; off >>= 1) na += __shfl_xor(na, off, 64);
+    if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
+}
+
 __global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol) {
     __shared__ double red[NT / WAVE];
     if (*s.any_active == 0) return;
@@ -366,6 +398,10 @@ hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
     const int nch = cg_chunks(n, w, s);
     hipLaunchKernelGGL(cg_alpha_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s);
     hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
+    return hipGetLastError();
+}
+hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s) {
+    hipLaunchKernelGGL(cg_alpha_tiles_kernel, dim3(1), dim3(1024), 0, st, w, ntiles, pq, s);
     return hipGetLastError();
 }
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol) {

@@ -56,7 +56,8 @@ def _spd(rng, d, cond):
     return (q * np.geomspace(1.0, cond, d)) @ q.T
 
 
-@pytest.mark.parametrize("d,cond", [(1, 1.0), (10, 10.0), (30, 1e3), (48, 1e4), (64, 1e2), (100, 1e3), (128, 1e5)])
+@pytest.mark.parametrize("d,cond", [(1, 1.0), (10, 10.0), (30, 1e3), (32, 10.0), (33, 1e2), (48, 1e4), (64, 1e2),
+                                    (65, 1e3), (100, 1e3), (127, 10.0), (128, 1e5)])
 def test_small_lrep_against_oracle(ctx, d, cond):
     rng = np.random.default_rng(d)
     Kh, Mh = _spd(rng, d, cond), _spd(rng, d, cond)
@@ -157,3 +158,23 @@ def test_input_ab_forms_k_and_m(ctx):
     L.lrep_test_apply(op, 1, Xd, Yd)
     np.testing.assert_allclose(host(Yd), (A + B) @ X, atol=1e-11)
     L.lrep_destroy_op(op)
+
+
+@pytest.mark.parametrize("d", [24, 96, 128])
+def test_small_lrep_clustered_spectrum(ctx, d):
+    """Clustered Ritz values (K^ = M^ = I + small symmetric noise): many
+    near-equal singular values of B, where Jacobi takes 45-degree rotations."""
+    rng = np.random.default_rng(7 * d)
+    e = rng.standard_normal((d, d)) * 1e-6
+    Kh = np.eye(d) + 0.5 * (e + e.T)
+    Mh = np.eye(d) + 1e-3 * np.diag(np.repeat([0.0, 1.0], (d + 1) // 2)[:d])
+    lam = torch.zeros(d, dtype=torch.float64, device="cuda:0")
+    Xh, Yh = dev_empty(128, 128, torch), dev_empty(128, 128, torch)
+    rc = L.lrep_test_small_lrep(ctx, dev_colmajor(Kh, torch), dev_colmajor(Mh, torch), lam, Xh, Yh)
+    assert rc == L.LREP_OK
+    lam_h, X, Y = host(lam), host(Xh)[:d, :d], host(Yh)[:d, :d]
+    ref, _, _ = oracle.small_lrep(Kh, Mh, d)
+    np.testing.assert_allclose(lam_h, ref, rtol=1e-13)
+    np.testing.assert_allclose(X.T @ Y, np.eye(d), atol=1e-12)
+    assert np.abs(Kh @ X - Y * lam_h).max() <= 1e-12
+    assert np.abs(Mh @ Y - X * lam_h).max() <= 1e-12
