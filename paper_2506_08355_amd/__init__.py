@@ -66,6 +66,8 @@ class lrep_solve_opts_t(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("rebiorth_tol", ctypes.c_double),
+        ("refresh", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -248,7 +250,7 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0, profile=False):
+              rebiorth_tol=0.0, profile=False, refresh=0):
     o = lrep_solve_opts_t()
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
@@ -257,6 +259,7 @@ def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=Non
     o.result_on_device = int(result_on_device)
     o.rebiorth_tol = rebiorth_tol
     o.profile = int(profile)
+    o.refresh = int(refresh)
     return o
 
 

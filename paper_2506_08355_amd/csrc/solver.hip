@@ -20,8 +20,12 @@
 //     column-by-column form needs w(w-1) grid-wide reductions per block.
 //   * the small problem's SVD is a one-sided Jacobi iteration in one
 //     workgroup (the paper uses a LAPACK SVD on the CPU).
-//   * every iteration re-applies K and M to the whole subspace, as the
-//     paper's cost model does (2d mat-vecs per Step 3).
+//   * K U and M V are applied afresh to the whole subspace only every
+//     `refresh` iterations (the paper's cost model re-applies them every
+//     iteration, 2d mat-vecs per Step 3); in between they follow the basis
+//     through the same coefficient products, and only the new W~, Z~ block
+//     is applied.  They are fresh again after every restoration of
+//     biorthogonality and before any pair is locked or returned.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -367,6 +371,10 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     int it = 0;
     const bool trace = std::getenv("LREP_TRACE") != nullptr;
     bool just_restored = false;
+    // K U and M V: applied afresh (need_fresh, or every o.refresh iterations)
+    // or carried through the basis updates for `carried` iterations
+    bool need_fresh = true;
+    int carried = 0;
     int rc = LREP_ENOTCONV;
     std::vector<double> epsc;
     while (it < o.maxit) {
@@ -383,10 +391,16 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         double* NMY = bMY[nxt].p;
         const int need = nev - c;
         // Step 3
-        CR(apply(0, U, d, KU));
-        CR(apply(1, V, d, MV));
-        stats.applies_K += d;
-        stats.applies_M += d;
+        if (need_fresh || carried >= o.refresh - 1) {
+            CR(apply(0, U, d, KU));
+            CR(apply(1, V, d, MV));
+            stats.applies_K += d;
+            stats.applies_M += d;
+            need_fresh = false;
+            carried = 0;
+        } else {
+            ++carried;
+        }
         CR(gram(segs({{U, n, d}}), segs({{KU, n, d}}), Kh, kMaxD, 1));
         CR(gram(segs({{V, n, d}}), segs({{MV, n, d}}), Mh, kMaxD, 1));
         CR(gram(segs({{U, n, d}}), segs({{V, n, d}}), S, kMaxD, 0));
@@ -426,6 +440,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             --it;
             stats.rebiorth++;
             just_restored = true;
+            need_fresh = true;
             CR(block_mgs(U, V, d, U, V, &kept));
             d = kept;
             continue;
@@ -436,6 +451,13 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
                 return fail(LREP_ENUMERIC, "non-finite Ritz value or residual");
         int p = 0;
         while (p < nr && hs->eps[p] <= tol) ++p;
+        if (carried > 0 && (p >= need || (p >= lock_unit && d > lock_unit))) {
+            // pairs are about to be locked or returned: judge them on images
+            // applied afresh to this subspace
+            --it;
+            need_fresh = true;
+            continue;
+        }
         if (p >= need) {
             // converged: X = [Xc, X~(:, 0:need)]
             CK(copy_cols(st, (int)n, need, NX, n, Xc.p + (size_t)c * n, n));
@@ -492,11 +514,13 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         stats.mgs_drops += nw - np;
         double* Pt = NX + (size_t)hi * n;
         double* Qt = NY + (size_t)hi * n;
+        // the next subspace's images are carried unless it starts with a refresh
+        const bool carry_next = carried < o.refresh - 1;
         {
-            const Seg A2[2] = {{U, n, d}, {V, n, d}};
-            const double* B2[2] = {Ph, Qh};
-            double* C2[2] = {Pt, Qt};
-            CK(gemm_nn_batch(st, (int)n, np, d, 2, A2, B2, kMaxD, C2, n, 1.0, 0.0));
+            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+            const double* B4[4] = {Ph, Qh, Ph, Qh};
+            double* C4[4] = {Pt, Qt, NKX + (size_t)hi * n, NMY + (size_t)hi * n};
+            CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, n, 1.0, 0.0));
         }
         // Step 6: block Gauss-Seidel sweeps with CG
         for (int j = 0; j < o.ngs; ++j) {
@@ -520,6 +544,13 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         // MGS-Biorth of (W~, Z~), appended after P~
         int nwk = 0;
         CR(block_mgs(Ws.p, Zs.p, nw, NX + (size_t)(hi + np) * n, NY + (size_t)(hi + np) * n, &nwk));
+        if (carry_next && nwk > 0) {
+            const size_t o2 = (size_t)(hi + np) * n;
+            CR(apply(0, NX + o2, nwk, NKX + o2));
+            CR(apply(1, NY + o2, nwk, NMY + o2));
+            stats.applies_K += nwk;
+            stats.applies_M += nwk;
+        }
         // Step 7
         cur = nxt;
         off = L;
@@ -599,6 +630,8 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
     if (o.cg_maxit <= 0) o.cg_maxit = 20;
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
+    if (o.refresh <= 0) o.refresh = 8;
+    if (o.reserved != 0) return LREP_EINVAL;
     if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
     s.o = o;
     s.b = (int)block;

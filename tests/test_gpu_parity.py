@@ -48,12 +48,18 @@ def check_pair(lam, X, Y, ref_lam, K_apply, M_apply, normH, bi_tol=1e-12, lam_to
     return res
 
 
-def test_config1_dense_n256(ctx):
+# refresh=1 applies K and M to the whole subspace every iteration (the paper's
+# cost model); the default carries the images between refreshes
+REFRESH = [pytest.param(1, id="refresh1"), pytest.param(0, id="refresh_default")]
+
+
+@pytest.mark.parametrize("refresh", REFRESH)
+def test_config1_dense_n256(ctx, refresh):
     n, nev, block, tol = 256, 8, 16, 1e-10
     K, M, f = gen.dense_operator(n, 1001)
     U, _ = gen.init_block(n, 3 * block, 7)
     op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
-    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U, refresh=refresh)
     L.lrep_destroy_op(op)
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     ref = oracle.bosp_solve(oracle.DenseOperator(K, M), nev, block, tol, init=(U, U))
@@ -108,13 +114,14 @@ def test_example_4_2_nullspace(ctx):
     assert np.abs(X0.T @ Y).max() <= 1e-11
 
 
-def test_zero_variant_role_swap_moving(ctx):
+@pytest.mark.parametrize("refresh", REFRESH)
+def test_zero_variant_role_swap_moving(ctx, refresh):
     n, nev, block, window, tol = 400, 24, 16, 8, 1e-10
     K, M, f = gen.dense_operator(n, 1012, n_zero_m=8)
     U, _ = gen.init_block(n, block + 2 * window, 7)
     op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), L.LREP_NULL_ON_M)
     L.lrep_set_nullspace(op, np.asfortranarray(f.null_basis_M()), ctx)
-    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U, refresh=refresh)
     L.lrep_destroy_op(op)
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     assert st.locks >= 1
@@ -125,12 +132,13 @@ def test_zero_variant_role_swap_moving(ctx):
     assert np.abs(f.null_basis_M().T @ X).max() <= 1e-10
 
 
-def test_casida_lowrank_moving(ctx):
+@pytest.mark.parametrize("refresh", REFRESH)
+def test_casida_lowrank_moving(ctx, refresh):
     n, r, nev, block, window, tol = 1500, 16, 32, 16, 8, 1e-9
     f = gen.casida_factors(n, r, 1003)
     U, _ = gen.init_block(n, block + 2 * window, 7)
     op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
-    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U, refresh=refresh)
     L.lrep_destroy_op(op)
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     cop = oracle.CasidaOperator(f.delta, f.L)
