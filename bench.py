@@ -12,15 +12,21 @@ positive eigenpairs, block 64, window 32 (moving mechanism), tolerance 1e-10.
 value = eigenpairs per second over the timed steps.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel (the FP64 MFMA block apply of the CG inner
-                solves, w = 32 columns) timed live with HIP events on the
-                solve's stream; algorithmic bytes 8 n^2 + 16 n w per launch
-                against the 8 TB/s HBM peak;
+  roofline      the dominant kernel (apply_stream_kernel, the FP64 MFMA block
+                apply of the CG inner solves, w = 32 columns) timed live with
+                HIP events on the solve's stream; algorithmic bytes
+                8 n^2 + 16 n w per launch against the 8 TB/s HBM peak.
+                `traffic` is the HBM bytes per launch measured with hardware
+                counters (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by
+                the same counters on a plain copy of known size), read from
+                the committed profile summary, and null when the kernel
+                source has changed since the counters were taken;
   cpu_baseline  the FP64 CPU oracle on the same operator for a bounded number
                 of outer iterations, scaled to eigenpairs/s by the number of
                 iterations the GPU solve needed.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +47,48 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_stream_kernel.dense8192.traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_08355_amd", "csrc", "apply.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the streaming apply from the committed counter
+    summary, if it was taken on this workload and on the current source."""
+    if workload != "dense8192" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if fields.get("apply_hip_sha256") != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """One plain device copy of `mib` MiB through the library's copy kernel
+    (reference for the byte counters); prints the bytes it moves."""
+    import torch
+    import paper_2506_08355_amd as L
+    count = mib * (1 << 20) // 8
+    src = torch.ones(count, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    ctx = L.lrep_init(0)
+    L.lrep_test_copy(ctx, src, dst)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(src, dst))
+    L.lrep_finalize(ctx)
+    print(json.dumps({"copy_kernel": "copy_kernel", "read_bytes": count * 8, "write_bytes": count * 8,
+                      "correct": ok}), flush=True)
+
+
 def describe(w):
     if w["kind"] == "dense":
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
@@ -57,9 +105,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-iters", type=int, default=8,
+    ap.add_argument("--cpu-iters", type=int, default=40,
                     help="outer iterations of the CPU oracle in the bounded baseline sample (0: skip)")
+    ap.add_argument("--operator-cache", default="", metavar="NPZ",
+                    help="dense workloads: load K, M from this .npz if it exists, else generate and save them "
+                         "(lets profiler passes skip the device QR of the generator)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the solver on a single MI355X; "
               "--gpus must be 1", file=sys.stderr)
@@ -77,7 +133,17 @@ def main():
     t0 = time.time()
     print(f"[bench] generating {args.workload} ...", file=sys.stderr, flush=True)
     if w["kind"] == "dense":
-        Kd, Md, kk, mm = gen.dense_operator_device(n, w["seed"], dev, n_zero_m=w["zeros"])
+        cache = args.operator_cache
+        if cache and os.path.exists(cache):
+            with np.load(cache, allow_pickle=False) as z:
+                if int(z["n"]) != n or int(z["seed"]) != w["seed"]:
+                    raise SystemExit(f"{cache} holds another workload")
+                Kd, Md = torch.from_numpy(z["K"]).to(dev), torch.from_numpy(z["M"]).to(dev)
+                kk, mm = z["k"], z["m"]
+        else:
+            Kd, Md, kk, mm = gen.dense_operator_device(n, w["seed"], dev, n_zero_m=w["zeros"])
+            if cache:
+                np.savez(cache, K=Kd.cpu().numpy(), M=Md.cpu().numpy(), k=kk, m=mm, n=n, seed=w["seed"])
         normH = float(max(kk.max(), mm.max()))
         null = None
         if w["zeros"]:
@@ -113,6 +179,7 @@ def main():
     lat = []
     prof_ms = prof_bytes = prof_flops = 0.0
     prof_launches = 0
+    phase_ms = [0.0] * 5
     iters = 0
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -123,6 +190,8 @@ def main():
         prof_bytes += st.prof_bytes
         prof_flops += st.prof_flops
         prof_launches += st.prof_launches
+        for k in range(5):
+            phase_ms[k] += st.phase_ms[k]
         iters = st.iterations
         print(f"[bench] step {i}: {lat[-1]:.1f} ms, {st.iterations} iterations, "
               f"applies K/M {st.applies_K}/{st.applies_M}", file=sys.stderr, flush=True)
@@ -153,9 +222,11 @@ def main():
     achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else None
     roofline = None
     if achieved is not None:
+        traffic = measured_traffic(args.workload)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "gemm_nn_kernel<128,32,4> (CG block apply, w=%d)" % window,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "algorithmic_bytes_per_launch": 8.0 * n * n + 16.0 * n * window,
+                    "kernel": "apply_stream_kernel (CG block apply, w=%d)" % window,
                     "launches": prof_launches, "avg_us": round(prof_ms * 1e3 / max(prof_launches, 1), 2),
                     "tflops": round(prof_flops / (prof_ms * 1e-3) / 1e12, 2),
                     "tflops_frac_fp64": round(prof_flops / (prof_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
@@ -192,6 +263,8 @@ def main():
                    "seed": w["seed"], "parallelism": "single GPU"},
         "p50_ms": round(lat_s[len(lat_s) // 2], 3), "p99_ms": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 3),
         "iterations": iters, "max_residual_Hnorm": max_res, "biorth": biorth,
+        "phase_ms_per_solve": dict(zip(["init", "small_problem", "convergence_check", "pq", "wz"],
+                                       [round(v / args.steps, 2) for v in phase_ms])),
         "roofline": roofline, "cpu_baseline": cpu,
     }
     L.lrep_destroy_op(op)

@@ -39,6 +39,11 @@ int lrep_test_block_mgs(lrep_ctx_t ctx, int n, int m, double* X, double* Y, int*
  * LREP_NULL_ON_M), X n x cols (ld n), Y n x cols (ld n). */
 int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* Y);
 
+/* dst[0:count] = src[0:count] (device FP64 arrays, 16-byte aligned): a
+ * plain streaming copy of known size, the reference against which hardware
+ * byte counters (FETCH_SIZE, WRITE_SIZE) are scaled. */
+int lrep_test_copy(lrep_ctx_t ctx, const double* src, double* dst, int64_t count);
+
 #ifdef __cplusplus
 }
 #endif

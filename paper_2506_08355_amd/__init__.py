@@ -136,6 +136,7 @@ _SIGS = {
     "lrep_test_small_lrep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _I64, _P, _P, _P]),
     "lrep_test_block_mgs": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "lrep_test_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lrep_test_copy": (ctypes.c_int, [_P, _P, _P, _I64]),
 }
 
 
@@ -356,3 +357,11 @@ def lrep_test_block_mgs(ctx, X, Y):
 def lrep_test_apply(op, which, X, Y):
     return _check(lib().lrep_test_apply(op, which, X.shape[1], colmajor(X)[0], colmajor(Y)[0]),
                   what="lrep_test_apply")
+
+
+def lrep_test_copy(ctx, src, dst):
+    """dst = src for two contiguous FP64 device tensors of the same even length."""
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in size")
+    return _check(lib().lrep_test_copy(ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                       src.numel()), ctx, "lrep_test_copy")

@@ -57,8 +57,11 @@ __global__ __launch_bounds__(256) void cg_dir_pack_kernel(int n, int w, double* 
                                                           const double* __restrict__ R,
                                                           const double* __restrict__ beta,
                                                           const int* __restrict__ active, int first,
-                                                          double* __restrict__ Pt, const int* __restrict__ flag) {
-    if (*flag == 0) return;
+                                                          double* __restrict__ Pt, const int* __restrict__ flag,
+                                                          int* __restrict__ flag_log) {
+    const int on = *flag;
+    if (flag_log && blockIdx.x == 0 && threadIdx.x == 0) *flag_log = on;
+    if (on == 0) return;
     __shared__ double tile[64][33];
     const int r0 = blockIdx.x * 64;
     for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
@@ -288,14 +291,14 @@ hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double*
 
 hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t lda, double* P, const double* R,
                           const double* beta, const int* active, int first, double* Q, double* pq, double* work,
-                          size_t work_elems, const int* any_active, hipEvent_t* ev) {
+                          size_t work_elems, const int* any_active, hipEvent_t* ev, int* flag_log) {
     if (w < 1 || w > 32 || n < 1 || (lda & 1) || (reinterpret_cast<uintptr_t>(A) & 15)) return hipErrorInvalidValue;
     StreamPlan pl;
     if (!plan_stream(n, n, work_elems, pl)) return hipErrorInvalidValue;
     double* Pt = work;
     double* part = work + (size_t)n * 32;
     hipLaunchKernelGGL(cg_dir_pack_kernel, dim3((n + 63) / 64), dim3(256), 0, st, n, w, P, R, beta, active, first, Pt,
-                       any_active);
+                       any_active, flag_log);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(apply_stream_kernel, dim3(pl.ntiles, pl.ksplit), dim3(64), 0, st, n, n, A, lda, Pt, pl.kchunk,
                        part, any_active);

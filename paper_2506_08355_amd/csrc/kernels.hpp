@@ -62,10 +62,11 @@ size_t stream_tiles(int m);
 // One CG step's operator work on the dense path (n x n, w <= 32 columns, all
 // ld n): p = r + beta p for the active columns (skipped when `first`), then
 // Q = A P, and pq[t * 32 + j] = the sum over tile t's rows of P[:, j] Q[:, j].
+// `flag_log` (optional) receives *any_active as the step starts.
 hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t lda, double* P,
                           const double* R, const double* beta, const int* active, int first,
                           double* Q, double* pq, double* work, size_t work_elems,
-                          const int* any_active, hipEvent_t* ev = nullptr);
+                          const int* any_active, hipEvent_t* ev = nullptr, int* flag_log = nullptr);
 
 // ---- vec.hip -------------------------------------------------------------
 // Y[:, j] = delta o X[:, j]

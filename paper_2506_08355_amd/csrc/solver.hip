@@ -99,9 +99,13 @@ struct Solver {
     ~Solver() {
         if (hs) (void)hipHostFree(hs);
         for (auto e : prof_ev) (void)hipEventDestroy(e);
+        for (auto e : mark_pool) (void)hipEventDestroy(e);
     }
 
-    hipEvent_t* prof_next(int cols) {
+    // events for the next timed apply; the "any column active" flag is
+    // logged by the caller's kernel into *slot when slot != nullptr, else
+    // copied here
+    hipEvent_t* prof_next(int cols, int** slot = nullptr) {
         const size_t i = prof_cols.size();
         if (!prof_log.p || i >= (size_t)kProfMax) return nullptr;
         while (prof_ev.size() < 2 * (i + 1)) {
@@ -110,7 +114,11 @@ struct Solver {
             prof_ev.push_back(e);
         }
         int* log = reinterpret_cast<int*>(prof_log.p);
-        if (hipMemcpyAsync(log + i, cg_any, sizeof(int), hipMemcpyDeviceToDevice, st) != hipSuccess) return nullptr;
+        if (slot) {
+            *slot = log + i;
+        } else if (hipMemcpyAsync(log + i, cg_any, sizeof(int), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            return nullptr;
+        }
         prof_cols.push_back(cols);
         return &prof_ev[2 * i];
     }
@@ -131,6 +139,32 @@ struct Solver {
             stats.prof_ms += ms;
             stats.prof_bytes += 8.0 * nn * nn + 16.0 * nn * c;
             stats.prof_flops += 2.0 * nn * nn * c;
+        }
+        return LREP_OK;
+    }
+
+    // per-phase GPU time (opts.profile): an event marks where each phase
+    // starts on the stream; the time to the next mark belongs to it
+    std::vector<std::pair<int, hipEvent_t>> marks;
+    std::vector<hipEvent_t> mark_pool;
+    void mark(int phase) {
+        if (!o.profile) return;
+        hipEvent_t e;
+        if (marks.size() < mark_pool.size()) {
+            e = mark_pool[marks.size()];
+        } else {
+            if (hipEventCreate(&e) != hipSuccess) return;
+            mark_pool.push_back(e);
+        }
+        if (hipEventRecord(e, st) == hipSuccess) marks.emplace_back(phase, e);
+    }
+    int collect_phases() {
+        if (marks.size() < 2) return LREP_OK;
+        CK(hipEventSynchronize(marks.back().second));
+        for (size_t i = 0; i + 1 < marks.size(); ++i) {
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, marks[i].second, marks[i + 1].second));
+            if (marks[i].first >= 0 && marks[i].first < 5) stats.phase_ms[marks[i].first] += ms;
         }
         return LREP_OK;
     }
@@ -245,11 +279,12 @@ struct Solver {
         const double* Ad = cg_stream_operator(which, nw);
         const int ntiles = (int)stream_tiles((int)n);
         for (int it = 0; it < maxit; ++it) {
-            hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw) : nullptr;
+            int* logslot = nullptr;
+            hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw, Ad ? &logslot : nullptr) : nullptr;
             if (Ad) {
                 // direction update of the previous step, pack, apply, p.q per tile
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
-                                  cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev));
+                                  cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
                 CK(cg_alpha_tiles(st, nw, ntiles, cg_pq, s));
                 CK(cg_update(st, (int)n, nw, s, cgtol));
             } else {
@@ -346,6 +381,9 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     const int d0 = b + 2 * w;
     int cur = 0, off = 0;
     int d = d0;
+    // phases: 0 initialise U, V / 1 small-scale problem (applies, projection,
+    // Ritz pairs, pull-back) / 2 convergence check / 3 P, Q / 4 W, Z
+    mark(0);
     // Step 1: starting block, V = U
     double* U0 = bX[0].p;
     double* V0 = bY[0].p;
@@ -391,6 +429,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         double* NMY = bMY[nxt].p;
         const int need = nev - c;
         // Step 3
+        mark(1);
         if (need_fresh || carried >= o.refresh - 1) {
             CR(apply(0, U, d, KU));
             CR(apply(1, V, d, MV));
@@ -420,6 +459,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         };
         CR(pull(0, nr, 0));
         // Step 4
+        mark(2);
         CK(residual_eps(st, (int)n, nr, NX, NY, NKX, NMY, n, lam, eps, part, (size_t)256 * kMaxD * 4, tickets));
         CK(hipMemcpyAsync(hs->eps, eps, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
         CK(hipMemcpyAsync(hs->lam, lam, sizeof(double) * d, hipMemcpyDeviceToHost, st));
@@ -487,6 +527,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             if (g >= nr || hs->eps[g] > tol) wg.push_back(g);
         for (int g = hi; g < d && (int)wg.size() < w; ++g) wg.push_back(g);
         // pull back what is not there yet: [nr, hi) at natural columns, extension g >= hi at g + 2w
+        mark(1);
         CR(pull(nr, hi, nr));
         for (int g : wg)
             if (g >= hi) CR(pull(g, g + 1, g + 2 * w));
@@ -508,6 +549,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CK(hipMemcpyAsync(wincol, wcol.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st));
         CK(hipMemcpyAsync(lamw, lw.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st));
         // Step 5
+        mark(3);
         CK(step5_pq(st, d, hi, Xh, Yh, win, nw, Ph, Qh, scr, status, MGS_COS_TOL, MGS_DEP_TOL, gwork.p, GEMM_WORK_ELEMS));
         CR(read_status());
         const int np = hs->status[ST_NP];
@@ -523,6 +565,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, n, 1.0, 0.0));
         }
         // Step 6: block Gauss-Seidel sweeps with CG
+        mark(4);
         for (int j = 0; j < o.ngs; ++j) {
             CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, n, NX, NMY, n, wincol, lamw, rhs.p, n));
             CR(cg(1, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
@@ -563,7 +606,11 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     stats.applies_M += (int64_t)hs->napplies[1];
     stats.iterations = it;
     stats.n_converged = c;
-    if (o.profile) CR(prof_collect());
+    mark(-1);
+    if (o.profile) {
+        CR(prof_collect());
+        CR(collect_phases());
+    }
     double me = 0;
     for (double e : epsc) me = std::max(me, e);
     stats.max_eps = me;

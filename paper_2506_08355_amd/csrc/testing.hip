@@ -12,6 +12,12 @@ int block_mgs_standalone(Ctx* c, hipStream_t st, int64_t n, int m, double* X, do
 }
 
 namespace {
+__global__ __launch_bounds__(256) void copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                  int64_t pairs) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
 int finish(Ctx* c, hipError_t e) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -87,6 +93,18 @@ int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* 
     rc = op_apply(op, c->stream, which, X, op->n, cols, Y, op->n, work.p, welems, small.p, nullptr);
     if (rc != LREP_OK) return rc;
     return finish(c, hipSuccess);
+}
+
+int lrep_test_copy(lrep_ctx_t ctx, const double* src, double* dst, int64_t count) {
+    if (!ctx || !src || !dst || count < 0 || (count & 1) || (reinterpret_cast<uintptr_t>(src) & 15) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15))
+        return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    const int64_t pairs = count / 2;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (pairs + 255) / 256));
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, ctx->stream, reinterpret_cast<const double2*>(src),
+                       reinterpret_cast<double2*>(dst), pairs);
+    return finish(ctx, hipGetLastError());
 }
 
 }  // extern "C"
