@@ -91,6 +91,11 @@ struct CgState {
     size_t part_elems;
     unsigned* ticket;          // 1
     unsigned long long* napplies;   // running count of column applies (active columns)
+    // optional host-visible note (mapped pinned memory): 2 seq + any_active,
+    // written whenever any_active is (re)computed, so that the host can stop
+    // issuing steps of solve `seq` once every column has converged
+    unsigned long long* note;
+    unsigned long long seq;
 };
 // x = 0, r = p = b (B may alias R), rr = bb = |b|^2, active = rr > tol^2 bb
 hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb,
@@ -99,6 +104,10 @@ hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double*
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s);
 // alpha from the per-tile sums written by cg_dense_apply (ntiles x 32)
 hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s);
+// cg_alpha_tiles and cg_update in one launch: every block forms alpha of its
+// column from the tile sums in the same fixed order
+hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
+                           double tol);
 // x += alpha p, r -= alpha q, rr_new, beta, active update
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
 // p = r + beta p for active columns

@@ -296,48 +296,55 @@ __device__ __forceinline__ double sumsq(const double (&x)[R]) {
     return qsum(s0 + s1);
 }
 
-// one rotation of the slot's pair (a, b) with norms (na, nb)
+// One rotation of the slot's pair.  The columns are kept scaled (Rutishauser's
+// fast form): the true columns are sa * a and sb * b, na and nb their squared
+// norms.  With the rotation  a' = c (a - t b),  b' = c (b + t a)  only the
+// scales take the factor c, and the stored vectors need two FMAs per row:
+//   a <- a - (t sb / sa) b,   b <- b + (t sa / sb) a_old,   sa, sb <- c sa, c sb.
 template <int R>
-__device__ __forceinline__ void jacobi_rotate(double (&a)[R], double (&b)[R], double& na, double& nb,
-                                              double& offmax) {
+__device__ __forceinline__ void jacobi_rotate(double (&a)[R], double (&b)[R], double& na, double& nb, double& sa,
+                                              double& sb, double& offmax) {
     double g0 = 0.0, g1 = 0.0;
 #pragma unroll
     for (int e = 0; e < R; e += 2) {
         g0 = fma(a[e], b[e], g0);
         g1 = fma(a[e + 1], b[e + 1], g1);
     }
-    const double ga = qsum(g0 + g1);
+    const double ga = qsum(g0 + g1) * (sa * sb);
     const double al = na, be = nb;
     const double rel = (ga != 0.0) ? fabs(ga) * rsq2(al * be) : 0.0;
     offmax = fmax(offmax, rel);
     const bool rot = rel > JACOBI_TOL;
     if (!__any(rot)) return;
-    // lanes whose pair needs no rotation apply the identity (c = 1, s = 0,
+    // lanes whose pair needs no rotation apply the identity (u = v = 0, c = 1,
     // exact), so that the update below runs unpredicated
-    double c = 1.0, s = 0.0, tg = 0.0;
+    double u = 0.0, v = 0.0, c = 1.0, tg = 0.0;
     if (rot) {
         // Rutishauser's rotation: zeta = (beta - alpha) / (2 gamma),
-        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t
+        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2)
         const double zeta = (be - al) * rcp2(2.0 * ga);
         const double az = fabs(zeta);
         const double w1 = fma(zeta, zeta, 1.0);
         const double root = az < 1e150 ? w1 * rsq2(w1) : az;
         const double t = copysign(rcp2(az + root), zeta);
         c = rsq2(fma(t, t, 1.0));
-        s = c * t;
+        u = t * sb * rcp2(sa);
+        v = t * sa * rcp2(sb);
         tg = t * ga;
     }
 #pragma unroll
     for (int e = 0; e < R; ++e) {
-        const double x = a[e], y = b[e];
-        a[e] = fma(c, x, -(s * y));
-        b[e] = fma(s, x, c * y);
+        const double x = a[e];
+        a[e] = fma(-u, b[e], x);
+        b[e] = fma(v, x, b[e]);
     }
+    sa *= c;
+    sb *= c;
     na = al - tg;
     nb = be + tg;
     const bool need = rot && ((na < 1e-2 * al) || (nb < 1e-2 * be));
     if (__any(need)) {   // heavy cancellation somewhere in the wavefront: exact norms
-        const double ea = sumsq<R>(a), eb = sumsq<R>(b);
+        const double ea = sumsq<R>(a) * (sa * sa), eb = sumsq<R>(b) * (sb * sb);
         if (need) {
             na = ea;
             nb = eb;
@@ -355,6 +362,7 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
     constexpr int NTH = NW * WAVE;
     __shared__ double xbuf[NW * R * WAVE];
     __shared__ double xnrm[NW * WAVE];
+    __shared__ double xscl[NW * WAVE];
     __shared__ double sig[D];
     __shared__ int rank_of[D];
     __shared__ double wmax[NW];
@@ -371,22 +379,24 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
         b[e] = (cb < d && row < d) ? Bm[(int64_t)cb * kMaxD + row] : 0.0;
     }
 
-    // exchange of b (and its norm) with wavefront w ^ kw
-    auto xwave_b = [&](int kw, double& nb) {
+    // exchange of b (with its norm and scale) with wavefront w ^ kw
+    auto xwave_b = [&](int kw, double& nb, double& sb) {
         double* mine = xbuf + (size_t)w * R * WAVE;
 #pragma unroll
         for (int e = 0; e < R; ++e) mine[e * WAVE + lane] = b[e];
         xnrm[w * WAVE + lane] = nb;
+        xscl[w * WAVE + lane] = sb;
         __syncthreads();
         const double* src = xbuf + (size_t)(w ^ kw) * R * WAVE;
 #pragma unroll
         for (int e = 0; e < R; ++e) b[e] = src[e * WAVE + lane];
         nb = xnrm[(w ^ kw) * WAVE + lane];
+        sb = xscl[(w ^ kw) * WAVE + lane];
         __syncthreads();
     };
     // level start: the lower slot's b <-> the upper slot's a (slots s, s ^ m)
-    auto relayout = [&](int m, double& na, double& nb) {
-        double sa = na, sb = nb;
+    auto relayout = [&](int m, double& na, double& nb, double& ca, double& cb) {
+        const double sa = na, sb = nb, fa = ca, fb = cb;
         if (m >= 16) {
             const int kw = m / 16;
             const bool up = (w & kw) != 0;
@@ -397,6 +407,7 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
                 mine[e * WAVE + lane] = up ? va : vb;
             }
             xnrm[w * WAVE + lane] = up ? sa : sb;
+            xscl[w * WAVE + lane] = up ? fa : fb;
             __syncthreads();
             const double* src = xbuf + (size_t)(w ^ kw) * R * WAVE;
 #pragma unroll
@@ -406,8 +417,11 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
                 b[e] = up ? vb : v;
             }
             const double vn = xnrm[(w ^ kw) * WAVE + lane];
+            const double vs = xscl[(w ^ kw) * WAVE + lane];
             na = up ? vn : sa;
             nb = up ? sb : vn;
+            ca = up ? vs : fa;
+            cb = up ? fb : vs;
             __syncthreads();
         } else {
             const bool up = (li & m) != 0;
@@ -423,6 +437,9 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
                 const double vn = xperm<K>(up ? sa : sb);
                 na = up ? vn : sa;
                 nb = up ? sb : vn;
+                const double vs = xperm<K>(up ? fa : fb);
+                ca = up ? vs : fa;
+                cb = up ? fb : vs;
             };
             if (m == 8) swap_with(std::integral_constant<int, 8>{});
             else if (m == 4) swap_with(std::integral_constant<int, 4>{});
@@ -432,29 +449,39 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
     };
 
     int sweeps = 0;
+    double sa = 1.0, sb = 1.0;   // column scales (fast rotations)
     for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
         ++sweeps;
+        // fold the scales back in and take exact norms at every sweep start
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            a[e] *= sa;
+            b[e] *= sb;
+        }
+        sa = sb = 1.0;
         double na = sumsq<R>(a), nb = sumsq<R>(b);
         double offmax = 0.0;
-        auto rot = [&]() { jacobi_rotate<R>(a, b, na, nb, offmax); };
+        auto rot = [&]() { jacobi_rotate<R>(a, b, na, nb, sa, sb, offmax); };
         auto mv = [&](auto kconst) {
             constexpr int K = decltype(kconst)::value;
 #pragma unroll
             for (int e = 0; e < R; ++e) b[e] = xperm<K>(b[e]);
             nb = xperm<K>(nb);
+            sb = xperm<K>(sb);
         };
         // levels with groups of 16 slots or more: b rotates by one lane inside
         // the 16-lane rows, and moves between wavefronts every 16 steps
         int L = 0;
         for (int G = S; G >= 16; G >>= 1, ++L) {
-            if (L > 0) relayout(G, na, nb);
+            if (L > 0) relayout(G, na, nb, sa, sb);
             for (int blk = 0; blk < G / 16; ++blk) {
-                if (blk > 0) xwave_b(1 << __builtin_ctz(blk), nb);
+                if (blk > 0) xwave_b(1 << __builtin_ctz(blk), nb, sb);
                 rot();
                 for (int u = 1; u < 16; ++u) {
 #pragma unroll
                     for (int e = 0; e < R; ++e) b[e] = dmov<0x121>(b[e]);   // row_ror:1
                     nb = dmov<0x121>(nb);
+                    sb = dmov<0x121>(sb);
                     rot();
                 }
             }
@@ -463,14 +490,14 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
         using I4 = std::integral_constant<int, 4>;
-        relayout(8, na, nb);
+        relayout(8, na, nb, sa, sb);
         rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
         mv(I4{}); rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
-        relayout(4, na, nb);
+        relayout(4, na, nb, sa, sb);
         rot(); mv(I1{}); rot(); mv(I2{}); rot(); mv(I1{}); rot();
-        relayout(2, na, nb);
+        relayout(2, na, nb, sa, sb);
         rot(); mv(I1{}); rot();
-        relayout(1, na, nb);
+        relayout(1, na, nb, sa, sb);
         rot();
         const double wm = wave_max(offmax);
         if (lane == 0) wmax[w] = wm;
@@ -481,13 +508,18 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
         __syncthreads();
         if (om <= JACOBI_TOL) break;
     }
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        a[e] *= sa;
+        b[e] *= sb;
+    }
     if (tid == 0 && status) status[ST_SWEEPS] = sweeps;
 
     // singular values, ranks (ascending sigma, position breaks ties), outputs
-    const double sa = sqrt(sumsq<R>(a)), sb = sqrt(sumsq<R>(b));
+    const double siga = sqrt(sumsq<R>(a)), sigb = sqrt(sumsq<R>(b));
     if (q == 0) {
-        sig[slot] = sa;
-        sig[S + slot] = sb;
+        sig[slot] = siga;
+        sig[S + slot] = sigb;
     }
     __syncthreads();
     for (int p = tid; p < D; p += NTH) {
@@ -767,6 +799,125 @@ __global__ __launch_bounds__(256) void coef_mgs_kernel(int m, const double* __re
     if (tid == 0) status[ST_NKEPT] = np;
 }
 
+// Coefficient pass of block MGS-Biorth for m <= CM columns: the recurrence of
+// coef_mgs_kernel (every inner product taken against the original Gram
+// blocks, which keeps the column form's accuracy on ill-conditioned inputs)
+// with the three Gram blocks and the coefficient vectors resident in LDS.
+// Four wavefronts: in each step wavefront p forms one of the four Gram
+// products (lane = row), wavefront 0 the pivot and norms, wavefronts 0 and 1
+// the coefficients r_j and s_j of the later columns (lane = j), and all
+// threads the right-looking update.
+constexpr int CM = 56;
+constexpr int CL = CM + 1;
+
+__global__ __launch_bounds__(256) void coef_mgs_lds_kernel(int m, const double* __restrict__ G, int64_t ldg,
+                                                           double* __restrict__ Aout, double* __restrict__ Bout,
+                                                           int* __restrict__ status, double cos_tol,
+                                                           double dep_tol) {
+    __shared__ double gxx[CM * CL], gxy[CM * CL], gyy[CM * CL];   // g[i * CL + k] = G(i, k)
+    __shared__ double A[CM * CL], B[CM * CL];                      // A[j * CL + i] = a_j[i]
+    __shared__ double tv[4][CM];                                   // Gxy b_l, Gxx a_l, Gyy b_l, Gxy^T a_l
+    __shared__ double rs[2][CM];
+    __shared__ double sc[4];
+    const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+    for (int idx = tid; idx < m * m; idx += 256) {
+        const int i = idx % m, k = idx / m;
+        gxx[i * CL + k] = G[(int64_t)k * ldg + i];
+        gxy[i * CL + k] = G[(int64_t)(m + k) * ldg + i];
+        gyy[i * CL + k] = G[(int64_t)(m + k) * ldg + (m + i)];
+        A[k * CL + i] = (i == k) ? 1.0 : 0.0;
+        B[k * CL + i] = (i == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int np = 0;
+    for (int l = 0; l < m; ++l) {
+        const double* al = A + l * CL;
+        const double* bl = B + l * CL;
+        // a_l, b_l are supported on rows 0..l
+        if (lane < m) {
+            const int i = lane;
+            const double* v = (wid == 1 || wid == 3) ? al : bl;
+            double s0 = 0.0, s1 = 0.0;
+            int k = 0;
+            if (wid == 3) {
+                for (; k + 1 <= l; k += 2) {
+                    s0 += gxy[k * CL + i] * v[k];
+                    s1 += gxy[(k + 1) * CL + i] * v[k + 1];
+                }
+                if (k == l) s0 += gxy[k * CL + i] * v[k];
+            } else {
+                const double* g = (wid == 0) ? gxy : (wid == 1 ? gxx : gyy);
+                for (; k + 1 <= l; k += 2) {
+                    s0 += g[i * CL + k] * v[k];
+                    s1 += g[i * CL + k + 1] * v[k + 1];
+                }
+                if (k == l) s0 += g[i * CL + k] * v[k];
+            }
+            tv[wid][i] = s0 + s1;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            double e = 0.0, p = 0.0, q = 0.0;
+            if (lane <= l) {
+                e = al[lane] * tv[0][lane];
+                p = al[lane] * tv[1][lane];
+                q = bl[lane] * tv[2][lane];
+            }
+            e = wave_sum(e);
+            p = wave_sum(p);
+            q = wave_sum(q);
+            if (lane == 0) {
+                sc[0] = e;
+                sc[1] = sqrt(fmax(p, 0.0));
+                sc[2] = sqrt(fmax(q, 0.0));
+            }
+        }
+        __syncthreads();
+        const double e = sc[0], pn = sc[1], qn = sc[2];
+        const double xn = sqrt(gxx[l * CL + l]), yn = sqrt(gyy[l * CL + l]);
+        if (e == 0.0 || fabs(e) <= cos_tol * pn * qn || pn <= dep_tol * xn || qn <= dep_tol * yn) continue;
+        const double sl = sqrt(fabs(e));
+        const double rl = e < 0 ? -sl : sl;
+        __syncthreads();   // all threads have read sc before it is reused
+        if (tid < m) {
+            const int i = tid;
+            const double av = (i <= l) ? al[i] / rl : 0.0, bv = (i <= l) ? bl[i] / sl : 0.0;
+            Aout[(int64_t)np * kMaxD + i] = av;
+            Bout[(int64_t)np * kMaxD + i] = bv;
+            if (i <= l) {
+                A[l * CL + i] = av;
+                B[l * CL + i] = bv;
+            }
+            tv[0][i] /= sl;   // Gxy b_l with the scaled b_l
+            tv[3][i] /= rl;   // Gxy^T a_l with the scaled a_l
+        }
+        ++np;
+        __syncthreads();
+        // r_j = (Gxy b_l) . a_j (wavefront 0), s_j = (Gxy^T a_l) . b_j (wavefront 1), j > l
+        if (wid < 2 && lane > l && lane < m) {
+            const int j = lane;
+            const double* t = (wid == 0) ? tv[0] : tv[3];
+            const double* c = (wid == 0) ? (A + j * CL) : (B + j * CL);
+            double s0 = 0.0, s1 = 0.0;
+            int i = 0;
+            for (; i + 1 <= j; i += 2) {
+                s0 += t[i] * c[i];
+                s1 += t[i + 1] * c[i + 1];
+            }
+            if (i == j) s0 += t[i] * c[i];
+            rs[wid][j] = s0 + s1;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (l + 1) * (m - l - 1); idx += 256) {
+            const int i = idx % (l + 1), j = l + 1 + idx / (l + 1);
+            A[j * CL + i] -= rs[0][j] * A[l * CL + i];
+            B[j * CL + i] -= rs[1][j] * B[l * CL + i];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) status[ST_NKEPT] = np;
+}
+
 }  // namespace
 
 hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh, int64_t ldh, double* lam,
@@ -827,6 +978,11 @@ hipError_t step5_pq(hipStream_t st, int d, int hi, const double* Xh, const doubl
 hipError_t coef_mgs(hipStream_t st, int m, const double* G, int64_t ldg, double* A, double* B, int* status,
                     double cos_tol, double dep_tol, double* scratch) {
     if (m > kMaxD) return hipErrorInvalidValue;
+    if (m <= CM) {
+        hipLaunchKernelGGL(coef_mgs_lds_kernel, dim3(1), dim3(256), 0, st, m, G, ldg, A, B, status, cos_tol,
+                           dep_tol);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(coef_mgs_kernel, dim3(1), dim3(256), 0, st, m, G, ldg, scratch, scratch + D2, A, B, status,
                        cos_tol, dep_tol);
     return hipGetLastError();

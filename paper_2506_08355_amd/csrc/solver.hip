@@ -87,6 +87,10 @@ struct Solver {
     unsigned* tickets;
     unsigned long long* napplies;
     HostStatus* hs = nullptr;
+    // host-visible CG note (mapped, coherent pinned memory) and its device alias
+    unsigned long long* note_h = nullptr;
+    unsigned long long* note_d = nullptr;
+    unsigned long long cg_seq = 0;
     std::string err;
     lrep_stats_t stats{};
     // profiling of the CG applies: event pairs, column counts and the CG
@@ -98,6 +102,7 @@ struct Solver {
 
     ~Solver() {
         if (hs) (void)hipHostFree(hs);
+        if (note_h) (void)hipHostFree(note_h);
         for (auto e : prof_ev) (void)hipEventDestroy(e);
         for (auto e : mark_pool) (void)hipEventDestroy(e);
     }
@@ -236,6 +241,9 @@ struct Solver {
         napplies = reinterpret_cast<unsigned long long*>(tickets + 8);
         CK(hipMemsetAsync(ismall.p, 0, ismall.bytes, st));
         CK(hipHostMalloc((void**)&hs, sizeof(HostStatus), hipHostMallocDefault));
+        CK(hipHostMalloc((void**)&note_h, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent));
+        *note_h = 0;
+        CK(hipHostGetDevicePointer((void**)&note_d, note_h, 0));
         if (o.profile) CR(prof_log.alloc(c, kProfMax * sizeof(int)));
         return LREP_OK;
     }
@@ -256,6 +264,8 @@ struct Solver {
         s.part_elems = (size_t)256 * kMaxD * 4;
         s.ticket = tickets + idx_ticket;
         s.napplies = napplies + which;
+        s.note = note_d;
+        s.seq = ++cg_seq;
         return s;
     }
 
@@ -279,14 +289,19 @@ struct Solver {
         const double* Ad = cg_stream_operator(which, nw);
         const int ntiles = (int)stream_tiles((int)n);
         for (int it = 0; it < maxit; ++it) {
+            // the device posts "no column active" for this solve: every step
+            // not yet issued would return at once, so stop issuing them
+            if (it > 0) {
+                const unsigned long long v = __atomic_load_n(note_h, __ATOMIC_ACQUIRE);
+                if ((v >> 1) == s.seq && (v & 1ull) == 0) break;
+            }
             int* logslot = nullptr;
             hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw, Ad ? &logslot : nullptr) : nullptr;
             if (Ad) {
                 // direction update of the previous step, pack, apply, p.q per tile
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
                                   cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
-                CK(cg_alpha_tiles(st, nw, ntiles, cg_pq, s));
-                CK(cg_update(st, (int)n, nw, s, cgtol));
+                CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
             } else {
                 CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
                 CK(lrep::cg_alpha(st, (int)n, nw, s));

@@ -111,7 +111,11 @@ __global__ __launch_bounds__(64) void cg_init_fin_kernel(int w, int nchunks, CgS
         any |= a;
     }
     any = __any(any) ? 1 : 0;
-    if (threadIdx.x == 0) *s.any_active = any;
+    if (threadIdx.x == 0) {
+        *s.any_active = any;
+        if (s.note) __hip_atomic_store(s.note, 2ull * s.seq + (unsigned long long)any, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks, CgState s) {
@@ -182,6 +186,43 @@ __global__ __launch_bounds__(1024) void cg_alpha_tiles_kernel(int w, int ntiles,
     if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
 }
 
+// alpha of column j from the tile sums (fixed order: thread t takes tiles
+// t, t + NT, ..., then the block sum), then x += alpha p, r -= alpha q and the
+// chunk's partial |r|^2.  Every block of a column computes the same alpha.
+__global__ __launch_bounds__(NT) void cg_update_tiles_kernel(int n, int w, int nchunks, int ntiles,
+                                                             const double* __restrict__ pq, CgState s, double tol) {
+    __shared__ double red[NT / WAVE];
+    if (*s.any_active == 0) return;
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    if (s.active[j]) {
+        double t = 0.0;
+        for (int k = threadIdx.x; k < ntiles; k += NT) t += pq[(int64_t)k * 32 + j];
+        t = block_sum<NT>(t, red);
+        if (ch == 0 && threadIdx.x == 0) atomicAdd(s.napplies, 1ull);
+        if (t > 0.0) {
+            const double a = s.rr[j] / t;
+            if (ch == 0 && threadIdx.x == 0) s.alpha[j] = a;
+            for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+                s.X[off + i] += a * s.P[off + i];
+                const double r = s.R[off + i] - a * s.Q[off + i];
+                s.R[off + i] = r;
+                acc += r * r;
+            }
+        } else {
+            // breakdown: p^T A p <= 0 (singular operator); the column stops and
+            // cg_update_fin leaves it inactive
+            if (ch == 0 && threadIdx.x == 0) s.alpha[j] = 0.0;
+            acc = -1.0;
+        }
+    }
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+}
+
 __global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol) {
     __shared__ double red[NT / WAVE];
     if (*s.any_active == 0) return;
@@ -219,7 +260,11 @@ __global__ __launch_bounds__(64) void cg_update_fin_kernel(int w, int nchunks, C
         }
     }
     any = __any(any) ? 1 : 0;
-    if (threadIdx.x == 0) *s.any_active = any;
+    if (threadIdx.x == 0) {
+        *s.any_active = any;
+        if (s.note) __hip_atomic_store(s.note, 2ull * s.seq + (unsigned long long)any, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __global__ __launch_bounds__(NT) void cg_direction_kernel(int n, int w, CgState s) {
@@ -402,6 +447,13 @@ hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
 }
 hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s) {
     hipLaunchKernelGGL(cg_alpha_tiles_kernel, dim3(1), dim3(1024), 0, st, w, ntiles, pq, s);
+    return hipGetLastError();
+}
+hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
+                           double tol) {
+    const int nch = cg_chunks(n, w, s);
+    hipLaunchKernelGGL(cg_update_tiles_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, ntiles, pq, s, tol);
+    hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol) {
