@@ -134,6 +134,8 @@ def main():
     print(f"[bench] generating {args.workload} ...", file=sys.stderr, flush=True)
     if w["kind"] == "dense":
         cache = args.operator_cache
+        if w["zeros"] and cache:
+            raise SystemExit("the operator cache does not hold the null basis of the zero variant")
         if cache and os.path.exists(cache):
             with np.load(cache, allow_pickle=False) as z:
                 if int(z["n"]) != n or int(z["seed"]) != w["seed"]:
@@ -141,13 +143,14 @@ def main():
                 Kd, Md = torch.from_numpy(z["K"]).to(dev), torch.from_numpy(z["M"]).to(dev)
                 kk, mm = z["k"], z["m"]
         else:
-            Kd, Md, kk, mm = gen.dense_operator_device(n, w["seed"], dev, n_zero_m=w["zeros"])
+            Kd, Md, kk, mm, _, Q2 = gen.dense_operator_device(n, w["seed"], dev, n_zero_m=w["zeros"],
+                                                               return_factors=True)
+            if w["zeros"]:
+                null = np.asfortranarray(Q2.cpu().numpy()[:, mm == 0.0])
+            del Q2
             if cache:
                 np.savez(cache, K=Kd.cpu().numpy(), M=Md.cpu().numpy(), k=kk, m=mm, n=n, seed=w["seed"])
         normH = float(max(kk.max(), mm.max()))
-        null = None
-        if w["zeros"]:
-            raise SystemExit("zero variant needs the null basis; use the parity tests")
     else:
         f = gen.casida_factors(n, w["rank"], w["seed"])
         delta_d = torch.from_numpy(f.delta).to(dev)
@@ -160,7 +163,9 @@ def main():
 
     ctx = L.lrep_init(0)
     if w["kind"] == "dense":
-        op = L.lrep_create_dense(ctx, Kd.T, Md.T)      # symmetric: the transpose view is column-major
+        op = L.lrep_create_dense(ctx, Kd.T, Md.T, L.LREP_NULL_ON_M if w["zeros"] else 0)
+        if w["zeros"]:
+            L.lrep_set_nullspace(op, null, ctx)     # the 8 columns of Q2 with m = 0
     else:
         op = L.lrep_create_lowrank(ctx, delta_d, L_d)
     lam = torch.zeros(nev, dtype=torch.float64, device=dev)
@@ -246,7 +251,8 @@ def main():
         else:
             cop = oracle.CasidaOperator(f.delta, f.L)
         tc = time.perf_counter()
-        r = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U0, U0), maxit=args.cpu_iters)
+        extra = dict(X0=null, null_on_M=True) if w.get("zeros") else {}
+        r = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U0, U0), maxit=args.cpu_iters, **extra)
         tcpu = time.perf_counter() - tc
         per_it = tcpu / max(r.iterations, 1)
         cpu = {"value": round(nev / (per_it * iters), 4), "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",

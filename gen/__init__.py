@@ -170,13 +170,14 @@ def init_block(n: int, d: int, seed: int):
 
 
 def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
-                          lo: float = 0.5, hi: float = 10.0):
+                          lo: float = 0.5, hi: float = 10.0, return_factors: bool = False):
     """The dense workload built on a torch device: the same NumPy draws in the
     same order as ``dense_factors`` (Gaussian for Q1, Gaussian for Q2, k, m),
     with the QR factorisations and the products K = Q1 diag(k) Q1^T,
     M = Q2 diag(m) Q2^T done by torch on ``device`` (for large n, where the
     host QR takes tens of seconds).  Returns (K, M, k, m) with K, M symmetric
-    FP64 device tensors and k, m NumPy vectors."""
+    FP64 device tensors and k, m NumPy vectors; with ``return_factors`` also
+    the device tensors Q1, Q2."""
     import torch
     rng = np.random.default_rng(seed)
     qs = []
@@ -195,4 +196,6 @@ def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
     for q, v in ((qs[0], k), (qs[1], m)):
         a = (q * torch.from_numpy(v).to(device)[None, :]) @ q.T
         out.append(0.5 * (a + a.T))
+    if return_factors:
+        return out[0], out[1], k, m, qs[0], qs[1]
     return out[0], out[1], k, m

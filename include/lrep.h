@@ -84,13 +84,16 @@ typedef struct lrep_solve_opts {
                                  the solve's stream (results in lrep_stats_t.prof_*)  */
     double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this
                               (default 1e-12)                                          */
-    int32_t refresh;       /* apply K and M afresh to the whole subspace every `refresh`
-                              iterations (default 8; 1 = every iteration).  In between,
-                              K U and M V follow the basis through the same coefficient
-                              products (Ritz pull-back, P~ = U P^) and only the new W~,
-                              Z~ block is applied; images are always fresh after a
-                              biorthogonality restoration and before pairs are locked
-                              or returned.                                             */
+    int32_t refresh;       /* longest interval, in iterations, between applications of
+                              K and M to the whole subspace (default 8; 1 = every
+                              iteration).  In between, K U and M V follow the basis
+                              through the same coefficient products (Ritz pull-back,
+                              P~ = U P^) and only the new W~, Z~ block is applied.
+                              The interval starts at 2 and adapts to the measured
+                              relative drift of the carried images (halved at
+                              1e-2 tol, doubled below 1e-3 tol); images are always
+                              fresh after a biorthogonality restoration and before
+                              pairs are locked or returned.                           */
     int32_t reserved;      /* must be 0                                                 */
 } lrep_solve_opts_t;
 

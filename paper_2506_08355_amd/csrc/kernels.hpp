@@ -120,6 +120,11 @@ hipError_t gs_rhs(hipStream_t st, int n, int w, const double* S, int64_t lds, co
                   const double* U, int64_t ldt, const int* win, const double* lam_w,
                   double* out, int64_t ldo);
 
+// max over the columns j of both pairs of |A_j - B_j| / |B_j| (n x cols, ld):
+// the relative drift of carried images A against fresh ones B
+hipError_t image_drift(hipStream_t st, int n, int cols, const double* A1, const double* B1, const double* A2,
+                       const double* B2, int64_t ld, double* part, size_t part_elems, double* out);
+
 // out = in, column block copy with leading dimensions
 hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out,
                      int64_t ldo);

@@ -63,6 +63,7 @@ struct HostStatus {
     double eps[kMaxD];
     double lam[kMaxD];
     double offmax;
+    double drift;
     int status[ST_COUNT];
     unsigned long long napplies[2];
 };
@@ -424,10 +425,16 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     int it = 0;
     const bool trace = std::getenv("LREP_TRACE") != nullptr;
     bool just_restored = false;
-    // K U and M V: applied afresh (need_fresh, or every o.refresh iterations)
-    // or carried through the basis updates for `carried` iterations
+    // K U and M V: applied afresh (need_fresh, or every `interval`
+    // iterations) or carried through the basis updates for `carried`
+    // iterations.  Each refresh after carried iterations measures how far the
+    // carried images drifted from the fresh ones; the interval halves when
+    // the drift reaches 1e-2 tol and doubles (up to o.refresh) below 1e-3 tol.
     bool need_fresh = true;
     int carried = 0;
+    int interval = std::min(2, o.refresh);
+    bool drift_pending = false;
+    double last_drift = 0.0;
     int rc = LREP_ENOTCONV;
     std::vector<double> epsc;
     while (it < o.maxit) {
@@ -445,9 +452,18 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         const int need = nev - c;
         // Step 3
         mark(1);
-        if (need_fresh || carried >= o.refresh - 1) {
-            CR(apply(0, U, d, KU));
-            CR(apply(1, V, d, MV));
+        if (need_fresh || carried >= interval - 1) {
+            if (carried > 0 && !need_fresh) {
+                CR(apply(0, U, d, tX.p));
+                CR(apply(1, V, d, tY.p));
+                CK(image_drift(st, (int)n, d, KU, tX.p, MV, tY.p, n, part, (size_t)256 * kMaxD * 4, offmax + 1));
+                CK(copy_cols(st, (int)n, d, tX.p, n, KU, n));
+                CK(copy_cols(st, (int)n, d, tY.p, n, MV, n));
+                drift_pending = true;
+            } else {
+                CR(apply(0, U, d, KU));
+                CR(apply(1, V, d, MV));
+            }
             stats.applies_K += d;
             stats.applies_M += d;
             need_fresh = false;
@@ -478,14 +494,24 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CK(residual_eps(st, (int)n, nr, NX, NY, NKX, NMY, n, lam, eps, part, (size_t)256 * kMaxD * 4, tickets));
         CK(hipMemcpyAsync(hs->eps, eps, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
         CK(hipMemcpyAsync(hs->lam, lam, sizeof(double) * d, hipMemcpyDeviceToHost, st));
-        CK(hipMemcpyAsync(&hs->offmax, offmax, sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipMemcpyAsync(&hs->offmax, offmax, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         CR(read_status());
         if (hs->status[ST_NOTSPD]) return fail(LREP_ENOTSPD, "Cholesky of a projected matrix failed");
+        if (drift_pending) {
+            drift_pending = false;
+            last_drift = hs->drift;
+            if (!(last_drift < 1e-2 * tol))
+                interval = std::max(1, interval / 2);
+            else if (last_drift < 1e-3 * tol)
+                interval = std::min(o.refresh, 2 * interval);
+        }
         if (trace) {
             double em = 0;
             for (int g = 0; g < nr; ++g) em = std::max(em, hs->eps[g]);
-            std::fprintf(stderr, "[lrep] it=%d d=%d locked=%d offmax=%.3e max_eps=%.3e lam0=%.15e sweeps=%d\n", it,
-                         d, c, hs->offmax, em, hs->lam[0], hs->status[ST_SWEEPS]);
+            std::fprintf(stderr,
+                         "[lrep] it=%d d=%d locked=%d offmax=%.3e max_eps=%.3e lam0=%.15e sweeps=%d carried=%d "
+                         "interval=%d drift=%.3e\n",
+                         it, d, c, hs->offmax, em, hs->lam[0], hs->status[ST_SWEEPS], carried, interval, last_drift);
         }
         // biorthogonality monitor: restore U^T V = I and redo the iteration (the
         // check is skipped on the pass right after a restore, as the check
@@ -571,8 +597,9 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         stats.mgs_drops += nw - np;
         double* Pt = NX + (size_t)hi * n;
         double* Qt = NY + (size_t)hi * n;
-        // the next subspace's images are carried unless it starts with a refresh
-        const bool carry_next = carried < o.refresh - 1;
+        // the next subspace's images are carried whenever carrying is on, also
+        // into a refresh, where they are compared with the fresh ones
+        const bool carry_next = interval > 1;
         {
             const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
             const double* B4[4] = {Ph, Qh, Ph, Qh};

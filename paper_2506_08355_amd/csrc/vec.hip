@@ -427,6 +427,50 @@ hipError_t residual_eps(hipStream_t st, int n, int cols, const double* X, const 
     return hipGetLastError();
 }
 
+// relative drift of carried operator images: per column of two pairs
+// (A1 vs B1, A2 vs B2) the partial sums of |a - b|^2 and |b|^2 over a chunk
+__global__ __launch_bounds__(NT) void drift_kernel(int n, int cols, int nchunks, const double* __restrict__ A1,
+                                                   const double* __restrict__ B1, const double* __restrict__ A2,
+                                                   const double* __restrict__ B2, int64_t ld,
+                                                   double* __restrict__ part) {
+    __shared__ double red[NT / WAVE];
+    const int j = blockIdx.y, ch = blockIdx.x, side = blockIdx.z;
+    const double* Aa = side ? A2 : A1;
+    const double* Bb = side ? B2 : B1;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    double dd = 0.0, bb = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+        const double b = Bb[(int64_t)j * ld + i];
+        const double e = Aa[(int64_t)j * ld + i] - b;
+        dd += e * e;
+        bb += b * b;
+    }
+    dd = block_sum<NT>(dd, red);
+    bb = block_sum<NT>(bb, red);
+    if (threadIdx.x == 0) {
+        double* p = part + (((int64_t)side * cols + j) * nchunks + ch) * 2;
+        p[0] = dd;
+        p[1] = bb;
+    }
+}
+
+__global__ __launch_bounds__(64) void drift_fin_kernel(int cols, int nchunks, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < 2 * cols; c += 64) {
+        double dd = 0.0, bb = 0.0;
+        for (int k = 0; k < nchunks; ++k) {
+            dd += part[((int64_t)c * nchunks + k) * 2];
+            bb += part[((int64_t)c * nchunks + k) * 2 + 1];
+        }
+        const double r = bb > 0.0 ? sqrt(dd / bb) : (dd > 0.0 ? INFINITY : 0.0);
+        mx = fmax(mx, r != r ? INFINITY : r);
+    }
+    mx = wave_max(mx);
+    if (threadIdx.x == 0) *out = mx;
+}
+
 static int cg_chunks(int n, int w, const CgState& s) {
     int nch = chunks_for(n, w);
     while ((size_t)nch * w > s.part_elems && nch > 1) nch /= 2;
@@ -508,6 +552,16 @@ hipError_t philox_normal(hipStream_t st, int n, int cols, uint64_t seed, double*
 hipError_t sign_normalise(hipStream_t st, int n, int cols, double* X, double* Y, int64_t ld) {
     if (cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(sign_normalise_kernel, dim3(cols), dim3(NT), 0, st, n, X, Y, ld);
+    return hipGetLastError();
+}
+
+hipError_t image_drift(hipStream_t st, int n, int cols, const double* A1, const double* B1, const double* A2,
+                       const double* B2, int64_t ld, double* part, size_t part_elems, double* out) {
+    if (cols <= 0) return hipSuccess;
+    int nch = chunks_for(n, cols);
+    while ((size_t)nch * cols * 4 > part_elems && nch > 1) nch /= 2;
+    hipLaunchKernelGGL(drift_kernel, dim3(nch, cols, 2), dim3(NT), 0, st, n, cols, nch, A1, B1, A2, B2, ld, part);
+    hipLaunchKernelGGL(drift_fin_kernel, dim3(1), dim3(64), 0, st, cols, nch, part, out);
     return hipGetLastError();
 }
 

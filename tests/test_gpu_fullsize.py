@@ -1,0 +1,105 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (same operators, start block, nev, block, window and tol).
+
+The oracle cannot run BOSP itself at these sizes in test time, so the GPU
+result is checked against what the oracle computes exactly for these
+workloads:
+  dense n = 8192       all 64 eigenvalues against the oracle's exact
+                       spectrum (smallest eigenvalues of F^T F,
+                       F = diag(sqrt k) Q1^T Q2 diag(sqrt m));
+  zero variant         the same with 8 exact zeros in m, plus the
+                       biorthogonality to the generalized null space;
+  Casida n = 262144    sampled eigenvalues bracketed by the oracle's
+                       Haynsworth inertia count (no eigenvalue skipped, each
+                       sampled one within 1e-10 relative of the k-th);
+and, for all, the FP64 residual ||H z - lambda z|| / (||H|| ||z||) <= 1e-8
+and max |Y^T X - I| <= 1e-12, evaluated on the host.
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import exact
+import paper_2506_08355_amd as L
+from gpu_util import h_residual
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    c = L.lrep_init(0)
+    yield c
+    L.lrep_finalize(c)
+
+
+def solve(ctx, op, n, nev, block, window, tol, init):
+    lam = np.zeros(nev)
+    X = np.zeros((n, nev), order="F")
+    Y = np.zeros((n, nev), order="F")
+    opts = L.make_opts(window=window, init=np.asfortranarray(init))
+    rc, st = L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx, check=False)
+    return rc, st, lam, X, Y
+
+
+@pytest.mark.parametrize("zeros,seed", [(0, 1002), (8, 1012)], ids=["dense8192", "dense8192_zero_variant"])
+def test_config2_full_size(ctx, zeros, seed):
+    n, nev, block, window, tol = 8192, 64, 64, 32, 1e-10
+    print(f"[fullsize] dense n={n} zeros={zeros} seed={seed}", flush=True)
+    Kd, Md, k, m, Q1, Q2 = gen.dense_operator_device(n, seed, "cuda:0", n_zero_m=zeros, return_factors=True)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    flags = L.LREP_NULL_ON_M if zeros else 0
+    op = L.lrep_create_dense(ctx, Kd.T, Md.T, flags)      # symmetric: the transpose view is column-major
+    q2 = Q2.cpu().numpy()
+    null = np.asfortranarray(q2[:, m == 0.0])
+    if zeros:
+        L.lrep_set_nullspace(op, null, ctx)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    K, M = Kd.cpu().numpy(), Md.cpu().numpy()
+    del Kd, Md
+    ref = exact.dense_spectrum_smallest(Q1.cpu().numpy(), k, q2, m, nev)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+    res = h_residual(lambda v: K @ v, lambda v: M @ v, X, Y, lam, float(max(k.max(), m.max())))
+    assert res.max() <= 1e-8, res.max()
+    assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12
+    if zeros:
+        # Lemma 2.3 (iii): the returned X is biorthogonal to the null space of M
+        assert np.abs(null.T @ X).max() <= 1e-10
+
+
+def test_config3_casida_full_size(ctx):
+    n, r, nev, block, window, tol = 262144, 256, 128, 64, 32, 1e-8
+    print(f"[fullsize] casida n={n} rank={r}", flush=True)
+    f = gen.casida_factors(n, r, 1003)
+    delta_d = torch.from_numpy(f.delta).to("cuda:0")
+    L_d = torch.from_numpy(np.ascontiguousarray(f.L.T)).to("cuda:0").T
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_lowrank(ctx, delta_d, L_d)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    Lh, dl = f.L, f.delta
+
+    def apply_M(v):
+        return dl[:, None] * v + 2.0 * (Lh @ (Lh.T @ v))
+
+    v = np.random.default_rng(5).standard_normal(n)
+    for _ in range(40):                      # ||M||_2 (>= ||K||_2 = max delta) by power iteration
+        v = apply_M(v[:, None])[:, 0]
+        v /= np.linalg.norm(v)
+    normH = float(v @ apply_M(v[:, None])[:, 0])
+    res = h_residual(lambda x: dl[:, None] * x, apply_M, X, Y, lam, normH)
+    assert res.max() <= 1e-8, res.max()
+    assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12
+    assert np.all(np.diff(lam) >= 0)
+    # sampled eigenvalues: exactly k - 1 eigenvalues lie below lam_k (1 - 1e-10)
+    # and at least k below lam_k (1 + 1e-10)
+    for kk in (1, 32, 64, 96, 128):
+        lk = lam[kk - 1]
+        assert exact.casida_count_below(dl, Lh, lk * (1 - 1e-10)) <= kk - 1, kk
+        assert exact.casida_count_below(dl, Lh, lk * (1 + 1e-10)) >= kk, kk

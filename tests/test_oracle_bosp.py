@@ -104,6 +104,19 @@ def test_dense_spectrum_against_bruteforce_eig():
     np.testing.assert_allclose(exact.dense_spectrum(f.q1, f.k, f.q2, f.m) ** 2, km, rtol=1e-10)
 
 
+def test_dense_spectrum_smallest_against_bruteforce():
+    """The F^T F route for large n against eig of H, with and without exact
+    zeros in m (the zero-eigenvalue variant)."""
+    for zeros in (0, 5):
+        K, M, f = gen.dense_operator(60, 12 + zeros, n_zero_m=zeros)
+        H = np.block([[np.zeros((60, 60)), K], [M, np.zeros((60, 60))]])
+        ev = np.sort(np.linalg.eigvals(H).real)
+        pos = ev[ev > 1e-6]
+        got = exact.dense_spectrum_smallest(f.q1, f.k, f.q2, f.m, 12)
+        np.testing.assert_allclose(got, pos[:12], rtol=1e-11)
+        np.testing.assert_allclose(got, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, 12), rtol=1e-12)
+
+
 def test_config1_dense_n256():
     """Dense n = 256, 8 smallest, block 16, tol 1e-10."""
     K, M, f = gen.dense_operator(256, 1001)
