@@ -228,10 +228,17 @@ def main():
     roofline = None
     if achieved is not None:
         traffic = measured_traffic(args.workload)
+        if w["kind"] == "dense":
+            kname = "apply_stream_kernel (CG block apply, w=%d)" % window
+            abytes = 8.0 * n * n + 16.0 * n * window
+        else:
+            kname = ("lowrank_lty_kernel + lty_reduce_kernel + apply_stream_kernel "
+                     "(low-rank M apply of the CG, w=%d, both passes)" % window)
+            abytes = 16.0 * n * w["rank"] + 24.0 * n * window
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "algorithmic_bytes_per_launch": 8.0 * n * n + 16.0 * n * window,
-                    "kernel": "apply_stream_kernel (CG block apply, w=%d)" % window,
+                    "algorithmic_bytes_per_launch": abytes,
+                    "kernel": kname,
                     "launches": prof_launches, "avg_us": round(prof_ms * 1e3 / max(prof_launches, 1), 2),
                     "tflops": round(prof_flops / (prof_ms * 1e-3) / 1e12, 2),
                     "tflops_frac_fp64": round(prof_flops / (prof_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}

@@ -95,9 +95,21 @@ __device__ __forceinline__ void mfma_step(d4 (&acc)[4][2], double2 x, double2 y,
     acc[3][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, b.y, acc[3][1], 0, 0, 0);
 }
 
+// Direct epilogue of an unsplit stream launch: C = alpha A X (+ delta o Yd).
+struct StreamOut {
+    double* C;
+    int64_t ldc;
+    int q;
+    double alpha;
+    const double* delta;
+    const double* Yd;
+    int64_t ldyd;
+};
+
 __global__ __launch_bounds__(64) void apply_stream_kernel(int m, int p, const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ Pt, int kchunk,
-                                                          double* __restrict__ part, const int* __restrict__ flag) {
+                                                          double* __restrict__ part, const int* __restrict__ flag,
+                                                          StreamOut so) {
     if (flag && *flag == 0) return;
     const int lane = threadIdx.x;
     const int tile = blockIdx.x, split = blockIdx.y;
@@ -171,12 +183,154 @@ __global__ __launch_bounds__(64) void apply_stream_kernel(int m, int p, const do
         }
         mfma_step(acc, x, y, b);
     }
+    if (so.C) {
+        // item v of fragment (fm, fn): row 32 (fm / 2) + 2 (4 v + kq) + fm % 2, column 2 c + fn
+#pragma unroll
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = row0 + 32 * (fm / 2) + 2 * (4 * v + kq) + (fm % 2);
+                    const int col = 2 * c + fn;
+                    if (row < m && col < so.q) {
+                        double o = so.alpha * acc[fm][fn][v];
+                        if (so.delta) o = fma(so.delta[row], so.Yd[(int64_t)col * so.ldyd + row], o);
+                        so.C[(int64_t)col * so.ldc + row] = o;
+                    }
+                }
+        return;
+    }
     const int ntiles = (m + WR - 1) / WR;
     double* out = part + (((int64_t)split * ntiles + tile) * WAVE + lane) * TV;
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
         for (int fn = 0; fn < 2; ++fn) *reinterpret_cast<d4*>(out + (fm * 2 + fn) * 4) = acc[fm][fn];
+}
+
+// ---------------------------------------------------------------------------
+// Low-rank M apply, first pass: T = L^T Y for L (n x r, r <= 256, ld even,
+// 16-byte aligned) and Y (n x w, w <= 32, ld even).  Workgroup g reduces rows
+// [g * chunk, (g + 1) * chunk); wavefront v owns L's columns [64 v, 64 v + 64)
+// (four 16-column fragments) and all 32 columns of Y (two fragments).  A lane
+// reads two consecutive rows of one column (16 bytes); the .x and .y halves
+// feed two MFMA k-steps, so a step of 8 rows is 16 v_mfma_f64_16x16x4_f64.
+// Partial T tiles are written in lane order and summed in a fixed order by
+// lty_reduce_kernel, which writes T k-major (r x 32) for the second pass.
+// ---------------------------------------------------------------------------
+constexpr int LPF = 2;   // 8-row steps per prefetch half
+
+__global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, const double* __restrict__ L,
+                                                          int64_t ldl, const double* __restrict__ Y, int64_t ldy,
+                                                          int chunk, double* __restrict__ part,
+                                                          const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int c = lane % 16, kq = lane / 16;
+    const int i_begin = blockIdx.x * chunk;
+    const int i_end = min(n, i_begin + chunk);
+    const int nfull = max(0, (i_end - i_begin) / 8);
+    d4 acc[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
+    // columns this lane reads (clamped into range; out-of-range ones are zeroed)
+    int lc[4];
+    bool lok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int col = 64 * wv + 16 * t + c;
+        lok[t] = col < r;
+        lc[t] = lok[t] ? col : 0;
+    }
+    const int yc0 = c, yc1 = 16 + c;
+    const bool yok0 = yc0 < w, yok1 = yc1 < w;
+    const double* lp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lp[t] = L + (int64_t)lc[t] * ldl + i_begin + 2 * kq;
+    const double* yp0 = Y + (int64_t)(yok0 ? yc0 : 0) * ldy + i_begin + 2 * kq;
+    const double* yp1 = Y + (int64_t)(yok1 ? yc1 : 0) * ldy + i_begin + 2 * kq;
+    if (nfull > 0) {
+        double2 a0[LPF][4], b0[LPF][2], a1[LPF][4], b1[LPF][2];
+        auto load = [&](double2 (&a)[LPF][4], double2 (&b)[LPF][2], int s0) {
+#pragma unroll
+            for (int j = 0; j < LPF; ++j) {
+                const int64_t o = (int64_t)min(s0 + j, nfull - 1) * 8;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[j][t] = *reinterpret_cast<const double2*>(lp[t] + o);
+                b[j][0] = *reinterpret_cast<const double2*>(yp0 + o);
+                b[j][1] = *reinterpret_cast<const double2*>(yp1 + o);
+            }
+        };
+        auto compute = [&](const double2 (&a)[LPF][4], const double2 (&b)[LPF][2], int s0) {
+#pragma unroll
+            for (int j = 0; j < LPF; ++j) {
+                const bool live = s0 + j < nfull;
+                double2 bb[2];
+                bb[0] = (live && yok0) ? b[j][0] : double2{0.0, 0.0};
+                bb[1] = (live && yok1) ? b[j][1] : double2{0.0, 0.0};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double2 aa = lok[t] ? a[j][t] : double2{0.0, 0.0};
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.x, bb[u].x, acc[t][u], 0, 0, 0);
+                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.y, bb[u].y, acc[t][u], 0, 0, 0);
+                    }
+                }
+            }
+        };
+        load(a0, b0, 0);
+        for (int s2 = 0; s2 < nfull; s2 += 2 * LPF) {
+            load(a1, b1, s2 + LPF);
+            compute(a0, b0, s2);
+            load(a0, b0, s2 + 2 * LPF);
+            compute(a1, b1, s2 + LPF);
+        }
+    }
+    // rows left over after the full 8-row steps (per-lane guards)
+    for (int i0 = i_begin + 8 * nfull; i0 < i_end; i0 += 8) {
+        const int ia = i0 + 2 * kq, ib = ia + 1;
+        double2 bb[2];
+        bb[0] = double2{(yok0 && ia < i_end) ? Y[(int64_t)yc0 * ldy + ia] : 0.0,
+                        (yok0 && ib < i_end) ? Y[(int64_t)yc0 * ldy + ib] : 0.0};
+        bb[1] = double2{(yok1 && ia < i_end) ? Y[(int64_t)yc1 * ldy + ia] : 0.0,
+                        (yok1 && ib < i_end) ? Y[(int64_t)yc1 * ldy + ib] : 0.0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double2 aa = {(lok[t] && ia < i_end) ? L[(int64_t)lc[t] * ldl + ia] : 0.0,
+                                (lok[t] && ib < i_end) ? L[(int64_t)lc[t] * ldl + ib] : 0.0};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.x, bb[u].x, acc[t][u], 0, 0, 0);
+                acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.y, bb[u].y, acc[t][u], 0, 0, 0);
+            }
+        }
+    }
+    double* out = part + ((int64_t)blockIdx.x * 256 + threadIdx.x) * 32;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) *reinterpret_cast<d4*>(out + (t * 2 + u) * 4) = acc[t][u];
+}
+
+// T (k-major, r x 32, zero-padded) = alpha * sum over the chunks of the
+// partial tiles, in a fixed order.  Thread x of block b handles entry
+// e = 256 b + x of the per-workgroup tile (lane-order layout of
+// lowrank_lty_kernel).
+__global__ __launch_bounds__(256) void lty_reduce_kernel(int r, int nchunk, const double* __restrict__ part,
+                                                         double alpha, double* __restrict__ Pt,
+                                                         const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;   // < 8192
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * 8192 + e];
+    const int tl = e / 32, v = e % 32;               // thread of the partial tile, item
+    const int wv = tl / WAVE, lane = tl % WAVE;
+    const int t = v / 8, u = (v / 4) % 2, it = v % 4;
+    const int row = 64 * wv + 16 * t + 4 * it + lane / 16;   // index into r
+    const int col = 16 * u + lane % 16;
+    if (row < r) Pt[(int64_t)row * 32 + col] = alpha * s;
 }
 
 // Sum of the split partial tiles: block (tile, g) of 256 threads writes rows
@@ -282,7 +436,7 @@ hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double*
     hipLaunchKernelGGL(pack_kmajor_kernel, dim3((p + 63) / 64), dim3(256), 0, st, p, q, X, ldx, Pt, active_flag);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(apply_stream_kernel, dim3(pl.ntiles, pl.ksplit), dim3(64), 0, st, m, p, A, lda, Pt, pl.kchunk,
-                       part, active_flag);
+                       part, active_flag, StreamOut{});
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(apply_reduce_kernel, dim3(pl.ntiles, (q + 7) / 8), dim3(256), 0, st, m, q, pl.ksplit, part, C, ldc, alpha,
                        beta, (const double*)nullptr, (int64_t)0, (double*)nullptr, active_flag);
@@ -301,10 +455,37 @@ hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t
                        any_active, flag_log);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(apply_stream_kernel, dim3(pl.ntiles, pl.ksplit), dim3(64), 0, st, n, n, A, lda, Pt, pl.kchunk,
-                       part, any_active);
+                       part, any_active, StreamOut{});
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(apply_reduce_kernel, dim3(pl.ntiles, 4), dim3(256), 0, st, n, w, pl.ksplit, part, Q, (int64_t)n,
                        1.0, 0.0, (const double*)P, (int64_t)n, pq, any_active);
+    return hipGetLastError();
+}
+
+hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* delta, const double* L, int64_t ldl,
+                           const double* Y, int64_t ldy, double* C, int64_t ldc, double* work, size_t work_elems,
+                           const int* active_flag, hipEvent_t* ev) {
+    if (w < 1 || w > 32 || r < 1 || r > 256 || n < 1 || (ldl & 1) || (ldy & 1) ||
+        (reinterpret_cast<uintptr_t>(L) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15))
+        return hipErrorInvalidValue;
+    // first pass: about one workgroup per CU, chunks of whole 8-row steps
+    int nchunk = std::max(1, std::min(256, n / 512));
+    int chunk = (n + nchunk - 1) / nchunk;
+    chunk = ((chunk + 8 * 2 * LPF - 1) / (8 * 2 * LPF)) * (8 * 2 * LPF);
+    nchunk = (n + chunk - 1) / chunk;
+    double* Pt = work;                        // r x 32
+    double* part = work + 256 * 32;           // nchunk x 8192
+    if ((size_t)256 * 32 + (size_t)nchunk * 8192 > work_elems) return hipErrorInvalidValue;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(lowrank_lty_kernel, dim3(nchunk), dim3(256), 0, st, n, r, w, L, ldl, Y, ldy, chunk, part,
+                       active_flag);
+    hipLaunchKernelGGL(lty_reduce_kernel, dim3(32), dim3(256), 0, st, r, nchunk, part, 2.0, Pt, active_flag);
+    // second pass: C = (2 L T) + delta o Y, unsplit stream with the direct epilogue
+    const int ntiles = (n + WR - 1) / WR;
+    const int kchunk = ((r + 3) / 4) * 4;
+    hipLaunchKernelGGL(apply_stream_kernel, dim3(ntiles, 1), dim3(64), 0, st, n, r, L, ldl, Pt, kchunk, part,
+                       active_flag, StreamOut{C, ldc, w, 1.0, delta, Y, ldy});
+    if (ev) (void)hipEventRecord(ev[1], st);
     return hipGetLastError();
 }
 

@@ -56,6 +56,14 @@ hipError_t dense_apply_narrow(hipStream_t st, int m, int q, int p, const double*
                               double beta, double* work, size_t work_elems,
                               const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
 
+// M Y for the low-rank operator M = diag(delta) + 2 L L^T (n x r, r <= 256,
+// w <= 32 columns; ld even, 16-byte aligned): T = 2 L^T Y by a streaming
+// MFMA reduction over n, then C = L T + delta o Y by the streaming apply with
+// a direct epilogue.  `ev` (optional) brackets both passes.
+hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* delta, const double* L,
+                           int64_t ldl, const double* Y, int64_t ldy, double* C, int64_t ldc, double* work,
+                           size_t work_elems, const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
+
 // 64-row tiles of the streaming apply for m rows
 size_t stream_tiles(int m);
 

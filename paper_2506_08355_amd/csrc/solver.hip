@@ -143,8 +143,14 @@ struct Solver {
             const double c = prof_cols[i];
             stats.prof_launches++;
             stats.prof_ms += ms;
-            stats.prof_bytes += 8.0 * nn * nn + 16.0 * nn * c;
-            stats.prof_flops += 2.0 * nn * nn * c;
+            if (op->kind == 0) {
+                stats.prof_bytes += 8.0 * nn * nn + 16.0 * nn * c;
+                stats.prof_flops += 2.0 * nn * nn * c;
+            } else {   // L read twice, Y read twice, result written once
+                const double r = (double)op->rank;
+                stats.prof_bytes += 16.0 * nn * r + 24.0 * nn * c;
+                stats.prof_flops += 4.0 * nn * r * c + 3.0 * nn * c;
+            }
         }
         return LREP_OK;
     }
@@ -297,7 +303,10 @@ struct Solver {
                 if ((v >> 1) == s.seq && (v & 1ull) == 0) break;
             }
             int* logslot = nullptr;
-            hipEvent_t* ev = (o.profile && op->kind == 0) ? prof_next(nw, Ad ? &logslot : nullptr) : nullptr;
+            // timed: the dense applies, and the low-rank M applies (the K applies of
+            // the low-rank operator are a diagonal scaling)
+            const bool timed = o.profile && (op->kind == 0 || ((which == 0) == op->null_on_M()));
+            hipEvent_t* ev = timed ? prof_next(nw, Ad ? &logslot : nullptr) : nullptr;
             if (Ad) {
                 // direction update of the previous step, pack, apply, p.q per tile
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
@@ -693,6 +702,15 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
         }
     } else if (useK) {
         e = diag_scale(st, (int)op->n, cols, op->delta, X, ldx, Y, ldy, active_flag);
+    } else if (op->rank <= 256 && (op->ldl % 2) == 0 && (ldx % 2) == 0 &&
+               (reinterpret_cast<uintptr_t>(op->L) % 16) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) {
+        // streaming low-rank apply, 32 columns at a time
+        for (int c0 = 0; c0 < cols && e == hipSuccess; c0 += 32) {
+            const int w = std::min(32, cols - c0);
+            e = lowrank_apply_M(st, (int)op->n, (int)op->rank, w, op->delta, op->L, op->ldl, X + (size_t)c0 * ldx,
+                                ldx, Y + (size_t)c0 * ldy, ldy, work, work_elems, active_flag,
+                                c0 == 0 ? ev : nullptr);
+        }
     } else {
         Seg Ls{op->L, op->ldl, (int)op->rank};
         Seg Xs{X, ldx, cols};

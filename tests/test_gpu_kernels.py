@@ -119,17 +119,33 @@ def test_block_mgs_drops_dependent_columns(ctx):
 
 
 @pytest.mark.parametrize("kind,n,cols", [("dense", 1500, 19), ("dense", 1501, 32), ("dense", 4096, 32),
-                                         ("dense", 700, 48), ("lowrank", 1500, 19), ("dense_swap", 1500, 19)])
+                                         ("dense", 700, 48), ("lowrank24", 1500, 19), ("lowrank24", 1501, 19),
+                                         ("lowrank256", 5002, 32),
+                                         ("lowrank100", 4098, 70), ("lowrank256", 262144, 32),
+                                         ("dense_swap", 1500, 19)])
 def test_operator_apply(ctx, kind, n, cols):
     """Dense applies with <= 32 columns and an even leading dimension take the
     streaming kernel (ragged row tiles at 1500), odd n and wide blocks the
-    tiled product."""
+    tiled product.  Low-rank M applies take the two streaming passes (L^T Y,
+    then L T + delta o Y) 32 columns at a time: rank below one wavefront's 64
+    columns, not a multiple of 16, the full 256; rows not a multiple of the
+    8-row step (5002: leftover rows and a ragged last row tile); odd n falls
+    back to the tiled product (1501); the full-size n = 262144."""
     rng = np.random.default_rng(5)
     Xh = rng.standard_normal((n, cols))
-    if kind == "lowrank":
-        f = gen.casida_factors(n, 24, 3)
+    if kind.startswith("lowrank"):
+        f = gen.casida_factors(n, int(kind[7:]), 3)
         op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
-        K, M = f.K(), f.M()
+        dl, Lf = f.delta, f.L
+
+        class _Op:   # K = diag(delta), M = diag(delta) + 2 L L^T without forming n x n
+            def __init__(self, m):
+                self.m = m
+
+            def __matmul__(self, x):
+                return dl[:, None] * x + (2.0 * (Lf @ (Lf.T @ x)) if self.m else 0.0)
+
+        K, M = _Op(False), _Op(True)
     else:
         K, M, _ = gen.dense_operator(n, 4)
         flags = L.LREP_NULL_ON_M if kind == "dense_swap" else 0
