@@ -266,18 +266,23 @@ __global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, c
 #pragma unroll
             for (int j = 0; j < LPF; ++j) {
                 const bool live = s0 + j < nfull;
-                double2 bb[2];
+                double2 bb[2], aa[4];
                 bb[0] = (live && yok0) ? b[j][0] : double2{0.0, 0.0};
                 bb[1] = (live && yok1) ? b[j][1] : double2{0.0, 0.0};
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const double2 aa = lok[t] ? a[j][t] : double2{0.0, 0.0};
+                for (int t = 0; t < 4; ++t) aa[t] = lok[t] ? a[j][t] : double2{0.0, 0.0};
+                // all eight accumulators once per k-step, so that no MFMA waits
+                // on the one just issued
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.x, bb[u].x, acc[t][u], 0, 0, 0);
-                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.y, bb[u].y, acc[t][u], 0, 0, 0);
-                    }
-                }
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t].x, bb[u].x, acc[t][u], 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t].y, bb[u].y, acc[t][u], 0, 0, 0);
             }
         };
         load(a0, b0, 0);
@@ -315,21 +320,33 @@ __global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, c
 }
 
 // T (k-major, r x 32, zero-padded) = alpha * sum over the chunks of the
-// partial tiles, in a fixed order.  Thread x of block b handles entry
-// e = 256 b + x of the per-workgroup tile (lane-order layout of
-// lowrank_lty_kernel).
+// partial tiles, in a fixed order.  Block b handles entries [64 b, 64 b + 64)
+// of the per-workgroup tile (lane-order layout of lowrank_lty_kernel): its
+// four wavefronts sum the chunks k = wv, wv + 4, ... for the 64 entries, then
+// wavefront 0 adds the four partial sums in order.
 __global__ __launch_bounds__(256) void lty_reduce_kernel(int r, int nchunk, const double* __restrict__ part,
                                                          double alpha, double* __restrict__ Pt,
                                                          const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;   // < 8192
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * 8192 + e];
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int e = blockIdx.x * 64 + lane;   // < 8192
+    double s0 = 0.0, s1 = 0.0;
+    int k = wv;
+    for (; k + 4 < nchunk; k += 8) {
+        s0 += part[(int64_t)k * 8192 + e];
+        s1 += part[(int64_t)(k + 4) * 8192 + e];
+    }
+    if (k < nchunk) s0 += part[(int64_t)k * 8192 + e];
+    red[wv][lane] = s0 + s1;
+    __syncthreads();
+    if (wv != 0) return;
+    const double s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     const int tl = e / 32, v = e % 32;               // thread of the partial tile, item
-    const int wv = tl / WAVE, lane = tl % WAVE;
+    const int pw = tl / WAVE, pl = tl % WAVE;
     const int t = v / 8, u = (v / 4) % 2, it = v % 4;
-    const int row = 64 * wv + 16 * t + 4 * it + lane / 16;   // index into r
-    const int col = 16 * u + lane % 16;
+    const int row = 64 * pw + 16 * t + 4 * it + pl / 16;   // index into r
+    const int col = 16 * u + pl % 16;
     if (row < r) Pt[(int64_t)row * 32 + col] = alpha * s;
 }
 
@@ -468,8 +485,8 @@ hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* de
     if (w < 1 || w > 32 || r < 1 || r > 256 || n < 1 || (ldl & 1) || (ldy & 1) ||
         (reinterpret_cast<uintptr_t>(L) & 15) || (reinterpret_cast<uintptr_t>(Y) & 15))
         return hipErrorInvalidValue;
-    // first pass: about one workgroup per CU, chunks of whole 8-row steps
-    int nchunk = std::max(1, std::min(256, n / 512));
+    // first pass: up to two workgroups per CU, chunks of whole prefetch rounds
+    int nchunk = std::max(1, std::min(512, n / 512));
     int chunk = (n + nchunk - 1) / nchunk;
     chunk = ((chunk + 8 * 2 * LPF - 1) / (8 * 2 * LPF)) * (8 * 2 * LPF);
     nchunk = (n + chunk - 1) / chunk;
@@ -479,7 +496,7 @@ hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* de
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(lowrank_lty_kernel, dim3(nchunk), dim3(256), 0, st, n, r, w, L, ldl, Y, ldy, chunk, part,
                        active_flag);
-    hipLaunchKernelGGL(lty_reduce_kernel, dim3(32), dim3(256), 0, st, r, nchunk, part, 2.0, Pt, active_flag);
+    hipLaunchKernelGGL(lty_reduce_kernel, dim3(128), dim3(256), 0, st, r, nchunk, part, 2.0, Pt, active_flag);
     // second pass: C = (2 L T) + delta o Y, unsplit stream with the direct epilogue
     const int ntiles = (n + WR - 1) / WR;
     const int kchunk = ((r + 3) / 4) * 4;

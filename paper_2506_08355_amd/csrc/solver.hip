@@ -579,8 +579,12 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         // pull back what is not there yet: [nr, hi) at natural columns, extension g >= hi at g + 2w
         mark(1);
         CR(pull(nr, hi, nr));
-        for (int g : wg)
-            if (g >= hi) CR(pull(g, g + 1, g + 2 * w));
+        {
+            // the extension indices are consecutive from hi: one batched pull
+            int ext = 0;
+            for (int g : wg) ext += g >= hi;
+            if (ext > 0) CR(pull(hi, hi + ext, hi + 2 * w));
+        }
         const int na = hi - L;
         if (wg.empty()) {
             cur = nxt;
