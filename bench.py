@@ -89,6 +89,96 @@ def copy_calibration(mib):
                       "correct": ok}), flush=True)
 
 
+def serve(args, np, torch, gen, L):
+    """Serving workload (continuous admission through lrep_submit/lrep_poll):
+    a pool of dense and low-rank operators, requests of random nev drawn 50/50
+    over them, first all at once (closed-loop solve rate), then with Poisson
+    arrivals at rho times that rate; latency = submit to completed poll.
+    Sizes are the serving configuration's ranges capped (dense n <= 8192,
+    low-rank n <= 32768) so that a run stays within a few minutes."""
+    rng = np.random.default_rng(1005)
+    dev = torch.device("cuda:0")
+    ctx = L.lrep_init(0)
+    pool, t0 = [], time.time()
+    for i in range(6):       # dense, n log-uniform [512, 8192], multiple of 64
+        n = int(64 * round(np.exp(rng.uniform(np.log(512), np.log(8192))) / 64))
+        Kd, Md, _, _ = gen.dense_operator_device(n, 2000 + i, dev)
+        pool.append((L.lrep_create_dense(ctx, Kd.T, Md.T), n))
+        del Kd, Md
+    for i in range(6):       # low rank, n log-uniform [16384, 32768], rank uniform {64..256}
+        n = int(64 * round(np.exp(rng.uniform(np.log(16384), np.log(32768))) / 64))
+        r = int(rng.integers(64, 257))
+        f = gen.casida_factors(n, r, 3000 + i)
+        pool.append((L.lrep_create_lowrank(ctx, torch.from_numpy(f.delta).to(dev),
+                                           torch.from_numpy(np.ascontiguousarray(f.L.T)).to(dev).T), n))
+    torch.cuda.synchronize()
+    print(f"[serve] operator pool ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    reqs = []
+    for i in range(args.requests):
+        k = int(rng.integers(0, 6)) + (6 if rng.uniform() < 0.5 else 0)
+        nev = int(rng.integers(4, 65))
+        block = 16 * ((nev + 15) // 16)
+        window = block // 2 if block >= 32 else block
+        reqs.append((k, nev, block, window))
+
+    def run(arrivals):
+        jobs, done = [], {}
+        start = time.perf_counter()
+        i = 0
+        pending = {}
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - start
+            while i < len(reqs) and arrivals[i] <= now:
+                k, nev, block, window = reqs[i]
+                op, n = pool[k]
+                lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+                opts = L.make_opts(window=window, seed=17 + i)
+                t = L.lrep_submit(ctx, op, nev, block, 1e-8, opts, lam, X, Y)
+                pending[t] = (i, time.perf_counter(), (lam, X, Y, opts))
+                i += 1
+            for t in list(pending):
+                rc, st = L.lrep_poll(ctx, t)
+                if rc == L.LREP_EAGAIN:
+                    continue
+                j, ts, _ = pending.pop(t)
+                done[j] = (rc, (time.perf_counter() - ts) * 1e3)
+                print(f"[serve] request {j} rc={rc} {done[j][1]:.0f} ms ({len(done)}/{len(reqs)})",
+                      file=sys.stderr, flush=True)
+            time.sleep(0.0005)
+        return time.perf_counter() - start, done
+
+    closed_time, closed = run([0.0] * len(reqs))
+    rate = len(reqs) / closed_time
+    gaps = rng.exponential(1.0 / (args.rho * rate), len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    open_time, done = run(list(arrivals))
+    lat = np.array([done[j][1] for j in range(len(reqs))])
+    ok = all(done[j][0] == L.LREP_OK for j in range(len(reqs))) and all(
+        closed[j][0] == L.LREP_OK for j in range(len(reqs)))
+    failed = [[j, done[j][0], pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
+              for j in range(len(reqs)) if done[j][0] != L.LREP_OK][:10]
+    slowest = sorted(range(len(reqs)), key=lambda j: -done[j][1])[:5]
+    slow = [[j, round(done[j][1], 1), pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
+            for j in slowest]
+    for op, _ in pool:
+        L.lrep_destroy_op(op)
+    L.lrep_finalize(ctx)
+    out = {
+        "metric": "serving: solves/s under Poisson arrivals; p50/p99 solve latency",
+        "value": round(len(reqs) / open_time, 3), "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 0, "ms_per_step": round(open_time * 1e3 / len(reqs), 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serving: 6 dense (n log-uniform 512-8192) + 6 low-rank (n log-uniform "
+                               "16384-32768, rank 64-256) operators, requests 50/50, nev uniform 4-64, tol 1e-8, "
+                               f"Poisson arrivals at rho={args.rho} of the closed-loop rate",
+                   "requests": len(reqs), "workers": 4},
+        "closed_loop_solves_per_s": round(rate, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "all_ok": ok, "failed": failed, "slowest": slow,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def describe(w):
     if w["kind"] == "dense":
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
@@ -104,7 +194,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dense8192", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dense8192", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--rho", type=float, default=0.7,
+                    help="serve: Poisson arrival rate as a fraction of the closed-loop solve rate")
     ap.add_argument("--cpu-iters", type=int, default=40,
                     help="outer iterations of the CPU oracle in the bounded baseline sample (0: skip)")
     ap.add_argument("--operator-cache", default="", metavar="NPZ",
@@ -127,6 +220,9 @@ def main():
     import gen
     import paper_2506_08355_amd as L
 
+    if args.workload == "serve":
+        serve(args, np, torch, gen, L)
+        return
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     n, nev, block, window, tol = w["n"], w["nev"], w["block"], w["window"], w["tol"]

@@ -214,8 +214,10 @@ int lrep_submit(lrep_ctx_t ctx, lrep_op_t op, const lrep_request_t* req, lrep_ti
  * reported, the ticket is released).  stats_out may be NULL. */
 int lrep_poll(lrep_ctx_t ctx, lrep_ticket_t ticket, lrep_stats_t* stats_out);
 
-/* Cancel a pending ticket (a running one finishes).  LREP_EINVAL for an
- * unknown ticket. */
+/* Cancel a ticket that is still queued: LREP_OK, and lrep_poll then reports
+ * LREP_ECANCELED.  A request already running (or finished) is not
+ * interrupted: LREP_EAGAIN, and lrep_poll reports its own outcome.
+ * LREP_EINVAL for an unknown ticket. */
 int lrep_cancel(lrep_ctx_t ctx, lrep_ticket_t ticket);
 
 /* ---------------------------------------------------------------- misc */

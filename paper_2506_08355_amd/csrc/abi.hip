@@ -337,10 +337,9 @@ int lrep_cancel(lrep_ctx_t c, lrep_ticket_t ticket) {
     std::lock_guard<std::mutex> g(c->q_mu);
     auto it = c->tickets.find(ticket);
     if (it == c->tickets.end()) return LREP_EINVAL;
-    if (it->second.state == 0) {
-        it->second.state = 3;
-        c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), ticket), c->queue.end());
-    }
+    if (it->second.state != 0) return LREP_EAGAIN;   // running or finished: not interrupted
+    it->second.state = 3;
+    c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), ticket), c->queue.end());
     return LREP_OK;
 }
 

@@ -1,0 +1,158 @@
+"""Serving interface (lrep_submit / lrep_poll / lrep_cancel): requests of
+different operators, sizes and nev run concurrently on the context's worker
+streams, admitted against the HBM budget.  Every kernel reduces in a fixed
+order and nothing in a solve depends on timing, so each result must be
+bitwise the one the same request gives alone."""
+import time
+
+import numpy as np
+import pytest
+
+import gen
+import paper_2506_08355_amd as L
+from gpu_util import dev_colmajor
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+# (operator, nev, block, window, tol)
+REQUESTS = [(0, 8, 16, 16, 1e-8), (1, 24, 32, 16, 1e-8), (2, 16, 16, 16, 1e-8), (0, 32, 32, 16, 1e-8),
+            (1, 4, 16, 16, 1e-8), (2, 40, 48, 24, 1e-8), (3, 12, 16, 8, 1e-8)]
+
+
+def make_ops(ctx):
+    ops, sizes = [], []
+    for n, seed in ((512, 1201), (1024, 1202)):
+        K, M, _ = gen.dense_operator(n, seed)
+        ops.append(L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch)))
+        sizes.append(n)
+    for n, r, seed in ((16384, 64, 1203), (20000, 100, 1204)):
+        f = gen.casida_factors(n, r, seed)
+        ops.append(L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch)))
+        sizes.append(n)
+    return ops, sizes
+
+
+def request_inputs(sizes):
+    out = []
+    for i, (o, nev, block, window, tol) in enumerate(REQUESTS):
+        U, _ = gen.init_block(sizes[o], block + 2 * window, 100 + i)
+        out.append(np.asfortranarray(U))
+    return out
+
+
+def run_alone(ctx, ops, sizes, inits):
+    res = []
+    for (o, nev, block, window, tol), U in zip(REQUESTS, inits):
+        n = sizes[o]
+        lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+        rc, st = L.lrep_solve(ops[o], n, nev, block, tol, L.make_opts(window=window, init=U), lam, X, Y, ctx=ctx)
+        assert rc == L.LREP_OK
+        res.append((lam, X, Y))
+    return res
+
+
+def run_mix(ctx, ops, sizes, inits, copies):
+    jobs = []
+    for c in range(copies):
+        for k, ((o, nev, block, window, tol), U) in enumerate(zip(REQUESTS, inits)):
+            n = sizes[o]
+            lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+            opts = L.make_opts(window=window, init=U)
+            t = L.lrep_submit(ctx, ops[o], nev, block, tol, opts, lam, X, Y)
+            jobs.append((k, t, lam, X, Y, opts))
+    pending = {j[1] for j in jobs}
+    deadline = time.time() + 240
+    saw_pending = False
+    while pending and time.time() < deadline:
+        for t in list(pending):
+            rc, st = L.lrep_poll(ctx, t)
+            if rc == L.LREP_EAGAIN:
+                saw_pending = True
+                continue
+            assert rc == L.LREP_OK, (rc, L.lrep_strerror(rc))
+            pending.discard(t)
+        time.sleep(0.005)
+    assert not pending, "served requests did not finish"
+    return jobs, saw_pending
+
+
+@pytest.fixture(scope="module")
+def served():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    ctx = L.lrep_init(0)
+    ops, sizes = make_ops(ctx)
+    inits = request_inputs(sizes)
+    alone = run_alone(ctx, ops, sizes, inits)
+    yield ctx, ops, sizes, inits, alone
+    for op in ops:
+        L.lrep_destroy_op(op)
+    L.lrep_finalize(ctx)
+
+
+def test_mix_is_bitwise_alone(served):
+    ctx, ops, sizes, inits, alone = served
+    jobs, saw_pending = run_mix(ctx, ops, sizes, inits, copies=2)
+    assert saw_pending   # the requests were in flight together
+    for k, t, lam, X, Y, _ in jobs:
+        a_lam, a_X, a_Y = alone[k]
+        assert np.array_equal(lam, a_lam), k
+        assert np.array_equal(X, a_X), k
+        assert np.array_equal(Y, a_Y), k
+
+
+def test_budget_admission_queues_and_matches():
+    """A context whose HBM budget holds the operators and about one solve's
+    workspace at a time: requests wait for memory instead of failing, and
+    still return the alone results."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    # size the budget from an unbudgeted context's per-solve footprint
+    probe = L.lrep_init(0)
+    ops, sizes = make_ops(probe)
+    inits = request_inputs(sizes)
+    alone = run_alone(probe, ops, sizes, inits)
+    for op in ops:
+        L.lrep_destroy_op(op)
+    L.lrep_finalize(probe)
+    op_bytes = sum(2 * n * n * 8 for n in sizes[:2]) + 16384 * 65 * 8 + 20000 * 101 * 8
+    budget = op_bytes + 400 * (1 << 20)   # the largest solve needs about 300 MiB
+    ctx = L.lrep_init(0, budget)
+    ops, sizes = make_ops(ctx)
+    try:
+        jobs, _ = run_mix(ctx, ops, sizes, inits, copies=1)
+        for k, t, lam, X, Y, _ in jobs:
+            a_lam, a_X, a_Y = alone[k]
+            assert np.array_equal(lam, a_lam), k
+            assert np.array_equal(X, a_X), k
+    finally:
+        for op in ops:
+            L.lrep_destroy_op(op)
+        L.lrep_finalize(ctx)
+
+
+def test_cancel_queued_request(served):
+    ctx, ops, sizes, inits, alone = served
+    # fill the workers, then cancel the last request while it is still queued
+    jobs = []
+    for i in range(6):
+        o, nev, block, window, tol = REQUESTS[5]
+        n = sizes[o]
+        lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+        opts = L.make_opts(window=window, init=inits[5])
+        jobs.append((L.lrep_submit(ctx, ops[o], nev, block, tol, opts, lam, X, Y), lam, X, Y, opts))
+    last = jobs[-1][0]
+    rc_cancel = L.lrep_cancel(ctx, last)
+    assert rc_cancel in (L.LREP_OK, L.LREP_EAGAIN)
+    deadline = time.time() + 240
+    for t, *_ in jobs:
+        while time.time() < deadline:
+            rc, _ = L.lrep_poll(ctx, t)
+            if rc != L.LREP_EAGAIN:
+                break
+            time.sleep(0.005)
+        if t == last and rc_cancel == L.LREP_OK:
+            assert rc == L.LREP_ECANCELED
+        else:
+            assert rc == L.LREP_OK
