@@ -43,6 +43,15 @@ WORKLOADS = {
     "dense8192z": dict(kind="dense", n=8192, seed=1012, nev=64, block=64, window=32, tol=1e-10, zeros=8),
     "dense256": dict(kind="dense", n=256, seed=1001, nev=8, block=16, window=16, tol=1e-10, zeros=0),
     "dense32768": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0),
+    # mixed precision (growth direction 1): BF16 / FP16 operator copies for the CG applies
+    "dense32768bf16": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                           precision=1),
+    "dense32768fp16": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                           precision=2),
+    "dense8192bf16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                          precision=1),
+    "dense8192fp16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                          precision=2),
     "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8),
 }
 
@@ -182,6 +191,8 @@ def serve(args, np, torch, gen, L):
 def describe(w):
     if w["kind"] == "dense":
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
+        z += {0: "", 1: "; CG applies in BF16 (f32 accumulate)", 2: "; CG applies in FP16 (f32 accumulate)"}[
+            w.get("precision", 0)]
         return (f"dense FP64 n={w['n']}: K=Q1 diag(k) Q1^T, M=Q2 diag(m) Q2^T, Haar Q1/Q2, k,m~U[0.5,10]{z}; "
                 f"nev={w['nev']}, block={w['block']}, window={w['window']}, tol={w['tol']:g}")
     return (f"Casida low-rank FP64 n={w['n']}: K=diag(delta), M=diag(delta)+2LL^T, delta~U[0.1,20] sorted, "
@@ -269,7 +280,7 @@ def main():
     Y = torch.zeros(nev, n, dtype=torch.float64, device=dev).T
 
     def step(profile):
-        opts = L.make_opts(window=window, init=U0d, profile=profile)
+        opts = L.make_opts(window=window, init=U0d, profile=profile, precision=w.get("precision", 0))
         rc, st = L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx)
         return st
 
@@ -324,7 +335,10 @@ def main():
     roofline = None
     if achieved is not None:
         traffic = measured_traffic(args.workload)
-        if w["kind"] == "dense":
+        if w["kind"] == "dense" and w.get("precision", 0):
+            kname = "apply16_stream_kernel (16-bit CG block apply, w=%d)" % window
+            abytes = 2.0 * n * n + 10.0 * n * window
+        elif w["kind"] == "dense":
             kname = "apply_stream_kernel (CG block apply, w=%d)" % window
             abytes = 8.0 * n * n + 16.0 * n * window
         else:
@@ -367,7 +381,10 @@ def main():
         "metric": "eigenpairs/s at 1e-8 residual; MFMA/HBM roofline fraction; p50/p99 solve latency",
         "value": round(value, 3), "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(total * 1e3 / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {0: "f64", 1: "bf16 CG applies (f32 accumulate), f64 elsewhere",
+                  2: "f16 CG applies (f32 accumulate), f64 elsewhere"}[w.get("precision", 0)],
+        "data": "synthetic",
         "config": {"workload": describe(w), "n": n, "nev": nev, "block": block, "window": window, "tol": tol,
                    "seed": w["seed"], "parallelism": "single GPU"},
         "p50_ms": round(lat_s[len(lat_s) // 2], 3), "p99_ms": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 3),

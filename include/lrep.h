@@ -18,6 +18,11 @@
  *     (ld >= number of rows);
  *   - pointers are host pointers unless a flag or option says "device"
  *     (a device pointer is a HIP device allocation on the context's device);
+ *   - the library runs on its own non-blocking streams (or the stream given
+ *     to lrep_init) and does not order itself after any other stream: the
+ *     data behind a device pointer must be complete when the call is made
+ *     (synchronize the stream that produced it first), and a blocking call
+ *     returns only after its device results are written;
  *   - every function returns 0 (LREP_OK) or a negative LREP_E* code and never
  *     aborts; lrep_strerror(code) gives a static message and
  *     lrep_last_error(ctx) the detail of the last failure on a context;
@@ -79,7 +84,16 @@ typedef struct lrep_solve_opts {
     int64_t ld_init;
     int32_t init_on_device;   /* init_U is a device pointer                             */
     int32_t result_on_device; /* lambda, X, Y are device pointers                       */
-    int32_t precision;        /* 0: FP64 everywhere (default)                          */
+    int32_t precision;        /* 0: FP64 everywhere (default).  Dense operators only:
+                                 1: the CG applies of Step 6 use a BF16 copy of K and
+                                 M and a BF16 copy of the CG block, FP32 accumulation
+                                 (MFMA), FP64 result; 2: the same in FP16 with each CG
+                                 column scaled by a power of two.  Everything else
+                                 (Rayleigh-Ritz images, residuals, MGS-Biorth, small
+                                 problem) stays FP64.  The 16-bit copies (2 n^2 bytes
+                                 each, charged to the context budget) are made at the
+                                 first such solve and kept with the operator; n must
+                                 be a multiple of 8.                                  */
     int32_t profile;          /* 1: time every Step-6 operator apply with HIP events on
                                  the solve's stream (results in lrep_stats_t.prof_*)  */
     double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this

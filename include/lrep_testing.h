@@ -39,6 +39,20 @@ int lrep_test_block_mgs(lrep_ctx_t ctx, int n, int m, double* X, double* Y, int*
  * LREP_NULL_ON_M), X n x cols (ld n), Y n x cols (ld n). */
 int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* Y);
 
+/* out (n x n, ld n, 16-bit) = the BF16 (precision 1) or FP16 (precision 2)
+ * copy of 0.5 (A + A^T) that the mixed-precision CG applies use: each
+ * value rounded to FP32, then to 16 bits, both to nearest even.  A is a
+ * device FP64 matrix (ld lda), out a device array of n * n 16-bit values. */
+int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, int64_t lda, uint16_t* out);
+
+/* Y = A16 X through the mixed-precision CG apply: A16 a 16-bit copy made as
+ * above, X scaled column by column by a power of two from rr[j] = |x_j|^2
+ * before its conversion when precision is 2 (FP16), FP32 accumulation, FP64
+ * result.  X, rr and Y are device arrays, X and Y n x cols (ld n),
+ * cols <= 32; n a multiple of 8, n >= 64. */
+int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint16_t* A16, const double* X,
+                      const double* rr, double* Y);
+
 /* dst[0:count] = src[0:count] (device FP64 arrays, 16-byte aligned): a
  * plain streaming copy of known size, the reference against which hardware
  * byte counters (FETCH_SIZE, WRITE_SIZE) are scaled. */

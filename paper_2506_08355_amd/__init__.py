@@ -136,6 +136,8 @@ _SIGS = {
     "lrep_test_small_lrep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _I64, _P, _P, _P]),
     "lrep_test_block_mgs": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "lrep_test_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lrep_test_convert16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _I64, _P]),
+    "lrep_test_apply16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
     "lrep_test_copy": (ctypes.c_int, [_P, _P, _P, _I64]),
 }
 
@@ -175,13 +177,24 @@ def _check(rc, ctx=None, what=""):
     return rc
 
 
+def _ready(x):
+    """The library does not order its streams after torch's: wait for the
+    work torch has queued on a device tensor's current stream, so that the
+    data behind the pointer is complete when the library reads it."""
+    if x.is_cuda:
+        import torch
+        torch.cuda.current_stream(x.device).synchronize()
+
+
 def colmajor(x):
-    """(pointer, leading dimension, on_device) of a column-major matrix/vector."""
+    """(pointer, leading dimension, on_device) of a column-major matrix/vector
+    (for a device tensor, after torch's queued work on it has finished)."""
     try:
         import torch
         if isinstance(x, torch.Tensor):
             if x.dtype != torch.float64:
                 raise TypeError("FP64 tensors required")
+            _ready(x)
             if x.dim() == 1:
                 if x.stride(0) != 1:
                     raise ValueError("vector must be contiguous")
@@ -251,7 +264,7 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0, profile=False, refresh=0):
+              rebiorth_tol=0.0, profile=False, refresh=0, precision=0):
     o = lrep_solve_opts_t()
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
@@ -261,6 +274,7 @@ def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=Non
     o.rebiorth_tol = rebiorth_tol
     o.profile = int(profile)
     o.refresh = int(refresh)
+    o.precision = int(precision)
     return o
 
 
@@ -359,9 +373,34 @@ def lrep_test_apply(op, which, X, Y):
                   what="lrep_test_apply")
 
 
+def lrep_test_convert16(ctx, precision, A, out):
+    """out (n * n 16-bit device tensor, column-major n x n) = the 16-bit copy
+    of the column-major FP64 device matrix A."""
+    p, ld, _ = colmajor(A)
+    n = A.shape[0]
+    if out.numel() != n * n or out.element_size() != 2:
+        raise ValueError("out must hold n * n 16-bit values")
+    _ready(out)
+    return _check(lib().lrep_test_convert16(ctx, precision, n, p, ld, ctypes.c_void_p(out.data_ptr())), ctx,
+                  "lrep_test_convert16")
+
+
+def lrep_test_apply16(ctx, precision, A16, X, rr, Y):
+    """Y = A16 X on a 16-bit copy (X, Y column-major device n x cols, rr the
+    device vector of squared column norms of X)."""
+    n, cols = X.shape
+    if A16.numel() != n * n or A16.element_size() != 2:
+        raise ValueError("A16 must hold n * n 16-bit values")
+    _ready(A16)
+    return _check(lib().lrep_test_apply16(ctx, precision, n, cols, ctypes.c_void_p(A16.data_ptr()),
+                                          colmajor(X)[0], ctypes.c_void_p(rr.data_ptr()), colmajor(Y)[0]),
+                  ctx, "lrep_test_apply16")
+
+
 def lrep_test_copy(ctx, src, dst):
     """dst = src for two contiguous FP64 device tensors of the same even length."""
     if src.numel() != dst.numel():
         raise ValueError("src and dst differ in size")
+    _ready(src)
     return _check(lib().lrep_test_copy(ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                        src.numel()), ctx, "lrep_test_copy")

@@ -51,6 +51,13 @@ struct Op {
     // generalized null space, biorthonormal X0^T Y0 = I (roles already exchanged)
     int64_t r0 = 0;
     DevBuf X0, Y0;
+    // 16-bit copies of a dense K and M for the mixed-precision CG applies
+    // (precision 1: BF16, 2: FP16), made on first use
+    std::mutex mu16;
+    int prec16 = 0;
+    DevBuf K16buf, M16buf;
+    const uint16_t* K16() const { return reinterpret_cast<const uint16_t*>(K16buf.p); }
+    const uint16_t* M16() const { return reinterpret_cast<const uint16_t*>(M16buf.p); }
     bool null_on_M() const { return (flags & LREP_NULL_ON_M) != 0; }
 };
 

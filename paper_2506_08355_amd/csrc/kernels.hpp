@@ -64,6 +64,18 @@ hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* de
                            int64_t ldl, const double* Y, int64_t ldy, double* C, int64_t ldc, double* work,
                            size_t work_elems, const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
 
+// ---- apply16.hip ---------------------------------------------------------
+// out (16-bit, n x n, ld n) = round(0.5 (A + A^T)); precision 1 = BF16, 2 = FP16
+hipError_t convert_operator16(hipStream_t st, int precision, int n, const double* A, int64_t lda,
+                              uint16_t* out);
+// The mixed-precision counterpart of cg_dense_apply: same contract, with the
+// product taken on the 16-bit operator copy A16 (n x n, n a multiple of 8)
+// and a 16-bit copy of P (FP16: columns scaled by powers of two from rr).
+hipError_t cg_dense_apply16(hipStream_t st, int precision, int n, int w, const uint16_t* A16, double* P,
+                            const double* R, const double* beta, const int* active, const double* rr,
+                            int first, double* Q, double* pq, double* work, size_t work_elems,
+                            const int* any_active, hipEvent_t* ev = nullptr, int* flag_log = nullptr);
+
 // 64-row tiles of the streaming apply for m rows
 size_t stream_tiles(int m);
 

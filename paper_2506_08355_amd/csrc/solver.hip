@@ -98,6 +98,7 @@ struct Solver {
     // "any column active" flag logged on the device just before each apply
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_cols;
+    std::vector<double> prof_b, prof_f;   // algorithmic bytes and flops of each timed launch
     DevBuf prof_log;
     static constexpr int kProfMax = 1 << 16;
 
@@ -111,7 +112,7 @@ struct Solver {
     // events for the next timed apply; the "any column active" flag is
     // logged by the caller's kernel into *slot when slot != nullptr, else
     // copied here
-    hipEvent_t* prof_next(int cols, int** slot = nullptr) {
+    hipEvent_t* prof_next(int cols, int** slot = nullptr, int prec = 0) {
         const size_t i = prof_cols.size();
         if (!prof_log.p || i >= (size_t)kProfMax) return nullptr;
         while (prof_ev.size() < 2 * (i + 1)) {
@@ -126,6 +127,18 @@ struct Solver {
             return nullptr;
         }
         prof_cols.push_back(cols);
+        const double nn = (double)n, c = cols;
+        if (op->kind == 0 && prec != 0) {   // 16-bit operator and block, FP64 result
+            prof_b.push_back(2.0 * nn * nn + 2.0 * nn * c + 8.0 * nn * c);
+            prof_f.push_back(2.0 * nn * nn * c);
+        } else if (op->kind == 0) {
+            prof_b.push_back(8.0 * nn * nn + 16.0 * nn * c);
+            prof_f.push_back(2.0 * nn * nn * c);
+        } else {   // low-rank M: L read twice, Y read twice, result written once
+            const double r = (double)op->rank;
+            prof_b.push_back(16.0 * nn * r + 24.0 * nn * c);
+            prof_f.push_back(4.0 * nn * r * c + 3.0 * nn * c);
+        }
         return &prof_ev[2 * i];
     }
 
@@ -140,17 +153,10 @@ struct Solver {
             if (!log[i]) continue;   // every column had converged: the launch returned at once
             float ms = 0.f;
             CK(hipEventElapsedTime(&ms, prof_ev[2 * i], prof_ev[2 * i + 1]));
-            const double c = prof_cols[i];
             stats.prof_launches++;
             stats.prof_ms += ms;
-            if (op->kind == 0) {
-                stats.prof_bytes += 8.0 * nn * nn + 16.0 * nn * c;
-                stats.prof_flops += 2.0 * nn * nn * c;
-            } else {   // L read twice, Y read twice, result written once
-                const double r = (double)op->rank;
-                stats.prof_bytes += 16.0 * nn * r + 24.0 * nn * c;
-                stats.prof_flops += 4.0 * nn * r * c + 3.0 * nn * c;
-            }
+            stats.prof_bytes += prof_b[i];
+            stats.prof_flops += prof_f[i];
         }
         return LREP_OK;
     }
@@ -295,6 +301,12 @@ struct Solver {
         CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
         const double* Ad = cg_stream_operator(which, nw);
         const int ntiles = (int)stream_tiles((int)n);
+        // mixed precision: the product on the 16-bit operator copy
+        const uint16_t* A16 = nullptr;
+        if (Ad && o.precision != 0 && op->prec16 == o.precision) {
+            const bool useK = (which == 0) != op->null_on_M();
+            A16 = useK ? op->K16() : op->M16();
+        }
         for (int it = 0; it < maxit; ++it) {
             // the device posts "no column active" for this solve: every step
             // not yet issued would return at once, so stop issuing them
@@ -306,8 +318,12 @@ struct Solver {
             // timed: the dense applies, and the low-rank M applies (the K applies of
             // the low-rank operator are a diagonal scaling)
             const bool timed = o.profile && (op->kind == 0 || ((which == 0) == op->null_on_M()));
-            hipEvent_t* ev = timed ? prof_next(nw, Ad ? &logslot : nullptr) : nullptr;
-            if (Ad) {
+            hipEvent_t* ev = timed ? prof_next(nw, Ad ? &logslot : nullptr, A16 ? o.precision : 0) : nullptr;
+            if (A16) {
+                CK(cg_dense_apply16(st, o.precision, (int)n, nw, A16, cgP.p, cgR.p, cg_beta, cg_active, cg_rr,
+                                    it == 0 ? 1 : 0, cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
+                CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
+            } else if (Ad) {
                 // direction update of the previous step, pack, apply, p.q per tile
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
                                   cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
@@ -742,7 +758,32 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.reserved != 0) return LREP_EINVAL;
+    if (o.reserved != 0 || o.precision < 0 || o.precision > 2) return LREP_EINVAL;
+    if (o.precision != 0 && op->kind == 0) {
+        // 16-bit copies of K and M for the mixed-precision CG applies
+        if (op->n % 8 != 0 || op->n < 64) return LREP_EINVAL;
+        std::lock_guard<std::mutex> g(op->mu16);
+        if (op->prec16 != o.precision) {
+            op->K16buf.release();
+            op->M16buf.release();
+            op->prec16 = 0;
+            const size_t bytes = (size_t)op->n * op->n * sizeof(uint16_t);
+            int rc = op->K16buf.alloc(op->ctx, bytes);
+            if (rc == LREP_OK) rc = op->M16buf.alloc(op->ctx, bytes);
+            if (rc != LREP_OK) return rc;
+            hipError_t e = convert_operator16(st, o.precision, (int)op->n, op->K, op->ld,
+                                              reinterpret_cast<uint16_t*>(op->K16buf.p));
+            if (e == hipSuccess)
+                e = convert_operator16(st, o.precision, (int)op->n, op->M, op->ld,
+                                       reinterpret_cast<uint16_t*>(op->M16buf.p));
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                op->ctx->set_error(hipGetErrorString(e));
+                return LREP_EDEVICE;
+            }
+            op->prec16 = o.precision;
+        }
+    }
     if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
     s.o = o;
     s.b = (int)block;

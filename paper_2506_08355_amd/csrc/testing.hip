@@ -95,6 +95,33 @@ int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* 
     return finish(c, hipSuccess);
 }
 
+int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, int64_t lda, uint16_t* out) {
+    if (!ctx || (precision != 1 && precision != 2) || n < 1 || lda < n || !A || !out) return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return finish(ctx, convert_operator16(ctx->stream, precision, n, A, lda, out));
+}
+
+int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint16_t* A16, const double* X,
+                      const double* rr, double* Y) {
+    if (!ctx || cols < 1 || cols > 32 || (precision != 1 && precision != 2) || n < 64 || (n % 8) != 0 || !A16 ||
+        !X || !rr || !Y)
+        return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    DevBuf work, pq, flag;
+    const size_t welems = size_t(8) << 20;
+    int rc = work.alloc(ctx, welems * sizeof(double));
+    if (rc == LREP_OK) rc = pq.alloc(ctx, stream_tiles(n) * 32 * sizeof(double));
+    if (rc == LREP_OK) rc = flag.alloc(ctx, sizeof(int));
+    if (rc != LREP_OK) return rc;
+    const int one = 1;
+    hipError_t e = hipMemcpyAsync(flag.p, &one, sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    // first step of a CG: the direction is X as given (not written), no beta / active read
+    if (e == hipSuccess)
+        e = cg_dense_apply16(ctx->stream, precision, n, cols, A16, const_cast<double*>(X), nullptr, nullptr, nullptr,
+                             rr, 1, Y, pq.p, work.p, welems, reinterpret_cast<const int*>(flag.p), nullptr, nullptr);
+    return finish(ctx, e);
+}
+
 int lrep_test_copy(lrep_ctx_t ctx, const double* src, double* dst, int64_t count) {
     if (!ctx || !src || !dst || count < 0 || (count & 1) || (reinterpret_cast<uintptr_t>(src) & 15) ||
         (reinterpret_cast<uintptr_t>(dst) & 15))

@@ -194,3 +194,83 @@ def test_small_lrep_clustered_spectrum(ctx, d):
     np.testing.assert_allclose(X.T @ Y, np.eye(d), atol=1e-12)
     assert np.abs(Kh @ X - Y * lam_h).max() <= 1e-12
     assert np.abs(Mh @ Y - X * lam_h).max() <= 1e-12
+
+
+
+def _round16(x, precision):
+    """Host rounding of FP64 values the way the 16-bit copies are made: one
+    rounding to nearest even straight to BF16 (8 significant bits, normal
+    exponents from -126) or FP16 (11 bits, from -14, subnormals below),
+    done in FP64 arithmetic (exact scaling by the quantum, then rint)."""
+    p, emin = (8, -126) if precision == 1 else (11, -14)
+    x = np.asarray(x, dtype=np.float64)
+    _, e = np.frexp(x)                        # |x| = f 2^e, f in [0.5, 1)
+    q = np.exp2(np.maximum(e - 1, emin) - (p - 1))
+    r = np.rint(x / q) * q                    # representable: the casts below are exact
+    return torch.from_numpy(r).to(torch.float32).to(_dtype16(precision))
+
+
+def _dtype16(precision):
+    return torch.bfloat16 if precision == 1 else torch.float16
+
+
+@pytest.mark.parametrize("precision", [1, 2], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("n", [64, 1000, 1001, 4104])
+def test_convert16_bitwise(ctx, precision, n):
+    """The 16-bit operator copy is bitwise the host's round-to-nearest-even of
+    the symmetric part: a non-symmetric input pins the transpose in the tiled
+    conversion, odd n and n = 1000 the ragged 32 x 32 tiles, a leading
+    dimension above n the strided reads; two conversions back to back into
+    two buffers must both be right."""
+    rng = np.random.default_rng(n)
+    lda = n + 3
+    outs = []
+    for rep in range(2):
+        A = rng.standard_normal((lda, n)) * (10.0 ** rng.uniform(-3, 3, (lda, n)))
+        Ad = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").T[:n]    # column-major, ld = lda
+        out = torch.empty(n * n, dtype=torch.int16, device="cuda:0")
+        L.lrep_test_convert16(ctx, precision, Ad, out)
+        outs.append((A[:n], out))
+    for A, out in outs:
+        S = 0.5 * (A + A.T)
+        want = _round16(S, precision).view(torch.int16).numpy()
+        got = out.cpu().numpy().reshape(n, n).T      # column-major n x n
+        assert np.array_equal(got, want), int((got != want).sum())
+
+
+@pytest.mark.parametrize("precision", [1, 2], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("n,cols", [(64, 5), (1000, 32), (4104, 19), (8192, 32)])
+def test_apply16_against_rounded_operands(ctx, precision, n, cols):
+    """The 16-bit CG apply equals the exact product of the rounded operands up
+    to FP32 accumulation (|err_i| <= n 2^-24 (|A16| |X16|)_i, X16 rounded on
+    the host the way the kernel rounds it), so a wrong fragment layout, split
+    or row tile shows as an O(1) error.  n = 1000 ends in a partial k-step, 4104
+    splits k four ways with a ragged last chunk and a ragged last row tile,
+    8192 is the dense workload's size.  FP16 scales each column by
+    2^round(log2 sqrt(n / |x_j|^2)) before rounding; columns of norm 1e-6 and
+    1e6 check that the scaling is applied and undone.  K and M go through
+    the same buffers one after the other."""
+    Kd, Md, _, _ = gen.dense_operator_device(n, 40 + n, "cuda:0")
+    rng = np.random.default_rng(n)
+    Xh = rng.standard_normal((n, cols))
+    Xh[:, 0] *= 1e-6
+    Xh[:, cols - 1] *= 1e6
+    rr = (Xh * Xh).sum(axis=0)
+    Xd = dev_colmajor(Xh, torch).T.contiguous().T
+    rrd = torch.from_numpy(rr).to("cuda:0")
+    Yd = dev_empty(n, cols, torch).T.contiguous().T
+    A16 = torch.empty(n * n, dtype=torch.int16, device="cuda:0")
+    sc = np.exp2(np.rint(0.5 * np.log2(n / rr))) if precision == 2 else np.ones(cols)
+    X16 = _round16(Xh * sc, precision).to(torch.float64).numpy()
+    for Ad in (Kd, Md):
+        L.lrep_test_convert16(ctx, precision, Ad.T, A16)
+        L.lrep_test_apply16(ctx, precision, A16, Xd, rrd, Yd)
+        A16h = A16.cpu().view(_dtype16(precision)).to(torch.float64).numpy().reshape(n, n).T
+        ref = (A16h @ X16) / sc
+        absprod = np.abs(A16h) @ np.abs(X16)
+        bound = n * 2.0 ** -24 * absprod / sc
+        err = np.abs(host(Yd) - ref)
+        assert np.all(err <= bound), float((err / bound).max())
+        # and the product is the operator's to 16-bit accuracy
+        exact = Ad.cpu().numpy() @ Xh
+        assert np.abs(host(Yd) - exact).max() <= 2e-2 * np.abs(exact).max()

@@ -53,13 +53,18 @@ def check_pair(lam, X, Y, ref_lam, K_apply, M_apply, normH, bi_tol=1e-12, lam_to
 REFRESH = [pytest.param(1, id="refresh1"), pytest.param(0, id="refresh_default")]
 
 
-@pytest.mark.parametrize("refresh", REFRESH)
-def test_config1_dense_n256(ctx, refresh):
+@pytest.mark.parametrize("refresh,precision", [pytest.param(1, 0, id="refresh1"),
+                                               pytest.param(0, 0, id="refresh_default"),
+                                               pytest.param(0, 1, id="bf16_cg_applies"),
+                                               pytest.param(0, 2, id="fp16_cg_applies")])
+def test_config1_dense_n256(ctx, refresh, precision):
+    """Also with the CG applies in BF16 / FP16 (FP32 accumulate): the other
+    steps stay FP64, so the eigenpairs must meet the same FP64 bars."""
     n, nev, block, tol = 256, 8, 16, 1e-10
     K, M, f = gen.dense_operator(n, 1001)
     U, _ = gen.init_block(n, 3 * block, 7)
     op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
-    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U, refresh=refresh)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U, refresh=refresh, precision=precision)
     L.lrep_destroy_op(op)
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     ref = oracle.bosp_solve(oracle.DenseOperator(K, M), nev, block, tol, init=(U, U))
