@@ -23,8 +23,13 @@ def ctx():
 
 @pytest.mark.parametrize("m,p,q,ksplit,beta", [
     (16, 4, 16, 0, 0.0), (300, 257, 33, 0, 0.0), (1000, 1000, 32, 4, 0.0), (129, 48, 16, 0, 0.5),
-    (517, 130, 100, 0, 0.0), (4096, 4096, 32, 0, 0.0), (2048, 2048, 128, 0, 0.0)])
+    (517, 130, 100, 0, 0.0), (4096, 4096, 32, 0, 0.0), (2048, 2048, 128, 0, 0.0),
+    (8192, 192, 64, 0, 0.5), (1000, 37, 19, 0, 0.0), (600, 1024, 8, 0, -1.0), (513, 3, 1, 0, 0.0)])
 def test_gemm_nn(ctx, m, p, q, ksplit, beta):
+    """Tall-skinny shapes (m >= 512, k <= 1024) take the register-direct
+    kernel: k in whole 16-deep units split over four waves plus a partial
+    unit (37, 130, 3), ragged row and column blocks (1000 x 19, 517 x 100);
+    large k and explicit splits take the LDS-tiled kernel."""
     rng = np.random.default_rng(m + p + q)
     A = rng.standard_normal((m, p))
     B = rng.standard_normal((p, q))
@@ -38,8 +43,12 @@ def test_gemm_nn(ctx, m, p, q, ksplit, beta):
 
 
 @pytest.mark.parametrize("n,p,q,sym", [(64, 16, 16, False), (5000, 70, 33, False), (8192, 128, 128, True),
-                                       (100003, 32, 64, False), (3, 5, 7, False)])
+                                       (100003, 32, 64, False), (3, 5, 7, False), (8192, 192, 32, False),
+                                       (1000, 257, 17, False), (513, 5, 3, False), (262144, 256, 64, False)])
 def test_gemm_tn(ctx, n, p, q, sym):
+    """n >= 512 takes the register-direct Gram kernel: row splits with a
+    ragged last unit (100003, 1000, 513), narrow (q <= 32) and wide column
+    blocks, ragged output blocks (257, 33, 17), symmetrisation."""
     rng = np.random.default_rng(n + p)
     A = rng.standard_normal((n, p))
     B = A[:, :q] + 0.1 * rng.standard_normal((n, q)) if sym else rng.standard_normal((n, q))
