@@ -426,7 +426,10 @@ bool plan_stream(int m, int p, size_t work_elems, StreamPlan& pl) {
     pl.tile_elems = (int64_t)pl.ntiles * WAVE * TV;
     if ((size_t)p * 32 + (size_t)pl.tile_elems > work_elems) return false;
     int ksplit = 1;
-    while (pl.ntiles * ksplit < 2048 && p / (ksplit * 2) >= 256 && ksplit < MAXSPLIT &&
+    // about 1024 workgroups, k chunks of at most 8192 columns (a longer
+    // stream per workgroup), each split adding a partial tile set to write
+    // and reduce
+    while ((pl.ntiles * ksplit < 1024 || p / ksplit > 8192) && p / (ksplit * 2) >= 256 && ksplit < MAXSPLIT &&
            (size_t)p * 32 + (size_t)(2 * ksplit) * pl.tile_elems <= work_elems)
         ksplit *= 2;
     // chunks of whole prefetch rounds (2 PF k-steps of 4 columns)

@@ -79,27 +79,27 @@ __global__ __launch_bounds__(NT) void residual_fin_kernel(int cols, int nchunks,
 }
 
 // ---------------------------------------------------------------- CG
-__global__ __launch_bounds__(NT) void cg_init_kernel(int n, int w, int nchunks, CgState s,
-                                                     const double* __restrict__ B, int64_t ldb, double tol) {
-    __shared__ double red[NT / WAVE];
-    const int j = blockIdx.y, ch = blockIdx.x;
-    const int rows = (n + nchunks - 1) / nchunks;
-    const int r0 = ch * rows, r1 = min(n, r0 + rows);
-    const int64_t off = (int64_t)j * n;
-    double acc = 0;
-    for (int i = r0 + threadIdx.x; i < r1; i += NT) {
-        const double b = B[(int64_t)j * ldb + i];
-        s.X[off + i] = 0.0;
-        s.R[off + i] = b;
-        s.P[off + i] = b;
-        acc += b * b;
+// Called by every block of a CG launch after its chunk sum is stored: true in
+// the block that arrives last (device-scope counter s.ticket, reset by that
+// block), which then runs the finishing step in its first wavefront.  Every
+// other block has read rr / active / any_active before it arrived, so the
+// finishing step may overwrite them.
+__device__ bool cg_arrive_last(const CgState& s) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned total = gridDim.x * gridDim.y;
+        last = atomicAdd(s.ticket, 1u) == total - 1 ? 1 : 0;
     }
-    acc = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) *s.ticket = 0u;
+    return true;
 }
 
-// one block: rr = bb = |b|^2, active = rr > tol^2 bb, any_active
-__global__ __launch_bounds__(64) void cg_init_fin_kernel(int w, int nchunks, CgState s, double tol) {
+// one wavefront: rr = bb = |b|^2, active = rr > tol^2 bb, any_active
+__device__ void cg_init_fin_wave(int w, int nchunks, const CgState& s, double tol) {
     int any = 0;
     for (int c = threadIdx.x; c < w; c += 64) {
         double t = 0;
@@ -118,23 +118,8 @@ __global__ __launch_bounds__(64) void cg_init_fin_kernel(int w, int nchunks, CgS
     }
 }
 
-__global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks, CgState s) {
-    __shared__ double red[NT / WAVE];
-    if (*s.any_active == 0) return;
-    const int j = blockIdx.y, ch = blockIdx.x;
-    const int rows = (n + nchunks - 1) / nchunks;
-    const int r0 = ch * rows, r1 = min(n, r0 + rows);
-    const int64_t off = (int64_t)j * n;
-    double acc = 0;
-    if (s.active[j])
-        for (int i = r0 + threadIdx.x; i < r1; i += NT) acc += s.P[off + i] * s.Q[off + i];
-    acc = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
-}
-
-// one block: alpha = rr / (p . q); a column with p^T A p <= 0 stops
-__global__ __launch_bounds__(64) void cg_alpha_fin_kernel(int w, int nchunks, CgState s) {
-    if (*s.any_active == 0) return;
+// one wavefront: alpha = rr / (p . q); a column with p^T A p <= 0 stops
+__device__ void cg_alpha_fin_wave(int w, int nchunks, const CgState& s) {
     int na = 0;
     for (int c = threadIdx.x; c < w; c += 64) {
         double a = 0.0;
@@ -152,6 +137,52 @@ __global__ __launch_bounds__(64) void cg_alpha_fin_kernel(int w, int nchunks, Cg
     // count the columns that received an apply (fixed-order wave sum of ints)
     for (int off = 32; off >= 1; off >>= 1) na += __shfl_xor(na, off, 64);
     if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
+}
+
+// finishing steps as launches of their own, for grids too large for one
+// device-scope arrival counter
+__global__ __launch_bounds__(64) void cg_init_fin_kernel(int w, int nchunks, CgState s, double tol) {
+    cg_init_fin_wave(w, nchunks, s, tol);
+}
+__global__ __launch_bounds__(64) void cg_alpha_fin_kernel(int w, int nchunks, CgState s) {
+    if (*s.any_active == 0) return;
+    cg_alpha_fin_wave(w, nchunks, s);
+}
+
+__global__ __launch_bounds__(NT) void cg_init_kernel(int n, int w, int nchunks, CgState s,
+                                                     const double* __restrict__ B, int64_t ldb, double tol,
+                                                     int fin) {
+    __shared__ double red[NT / WAVE];
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    for (int i = r0 + threadIdx.x; i < r1; i += NT) {
+        const double b = B[(int64_t)j * ldb + i];
+        s.X[off + i] = 0.0;
+        s.R[off + i] = b;
+        s.P[off + i] = b;
+        acc += b * b;
+    }
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (fin && cg_arrive_last(s) && threadIdx.x < 64) cg_init_fin_wave(w, nchunks, s, tol);
+}
+
+__global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks, CgState s, int fin) {
+    __shared__ double red[NT / WAVE];
+    if (*s.any_active == 0) return;
+    const int j = blockIdx.y, ch = blockIdx.x;
+    const int rows = (n + nchunks - 1) / nchunks;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double acc = 0;
+    if (s.active[j])
+        for (int i = r0 + threadIdx.x; i < r1; i += NT) acc += s.P[off + i] * s.Q[off + i];
+    acc = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (fin && cg_arrive_last(s) && threadIdx.x < 64) cg_alpha_fin_wave(w, nchunks, s);
 }
 
 // alpha_fin on the per-tile p.q sums of the fused dense path: thread
@@ -186,11 +217,37 @@ __global__ __launch_bounds__(1024) void cg_alpha_tiles_kernel(int w, int ntiles,
     if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
 }
 
-// alpha of column j from the tile sums (fixed order: thread t takes tiles
-// t, t + NT, ..., then the block sum), then x += alpha p, r -= alpha q and the
-// chunk's partial |r|^2.  Every block of a column computes the same alpha.
+// beta, rr, active and any_active from the per-chunk sums of |r|^2, run by
+// one wavefront (lanes over columns)
+__device__ void cg_fin_wave(int w, int nchunks, const CgState& s, double tol) {
+    int any = 0;
+    for (int c = threadIdx.x; c < w; c += 64) {
+        if (s.active[c]) {
+            double t = 0;
+            for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
+            s.beta[c] = t / s.rr[c];
+            s.rr[c] = t;
+            const int a = t > tol * tol * s.bb[c] ? 1 : 0;
+            s.active[c] = a;
+            any |= a;
+        }
+    }
+    any = __any(any) ? 1 : 0;
+    if (threadIdx.x == 0) {
+        *s.any_active = any;
+        if (s.note) __hip_atomic_store(s.note, 2ull * s.seq + (unsigned long long)any, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__global__ __launch_bounds__(64) void cg_update_fin_kernel(int w, int nchunks, CgState s, double tol) {
+    if (*s.any_active == 0) return;
+    cg_fin_wave(w, nchunks, s, tol);
+}
+
 __global__ __launch_bounds__(NT) void cg_update_tiles_kernel(int n, int w, int nchunks, int ntiles,
-                                                             const double* __restrict__ pq, CgState s, double tol) {
+                                                             const double* __restrict__ pq, CgState s, double tol,
+                                                             int fin) {
     __shared__ double red[NT / WAVE];
     if (*s.any_active == 0) return;
     const int j = blockIdx.y, ch = blockIdx.x;
@@ -221,9 +278,10 @@ __global__ __launch_bounds__(NT) void cg_update_tiles_kernel(int n, int w, int n
     }
     acc = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (fin && cg_arrive_last(s) && threadIdx.x < 64) cg_fin_wave(w, nchunks, s, tol);
 }
 
-__global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol) {
+__global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks, CgState s, double tol, int fin) {
     __shared__ double red[NT / WAVE];
     if (*s.any_active == 0) return;
     const int j = blockIdx.y, ch = blockIdx.x;
@@ -242,31 +300,10 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int n, int w, int nchunks
     }
     acc = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) s.part[(int64_t)j * nchunks + ch] = acc;
+    if (fin && cg_arrive_last(s) && threadIdx.x < 64) cg_fin_wave(w, nchunks, s, tol);
 }
 
 // one block: beta, rr, active (relative residual test), any_active
-__global__ __launch_bounds__(64) void cg_update_fin_kernel(int w, int nchunks, CgState s, double tol) {
-    if (*s.any_active == 0) return;
-    int any = 0;
-    for (int c = threadIdx.x; c < w; c += 64) {
-        if (s.active[c]) {
-            double t = 0;
-            for (int k = 0; k < nchunks; ++k) t += s.part[(int64_t)c * nchunks + k];
-            s.beta[c] = t / s.rr[c];
-            s.rr[c] = t;
-            const int a = t > tol * tol * s.bb[c] ? 1 : 0;
-            s.active[c] = a;
-            any |= a;
-        }
-    }
-    any = __any(any) ? 1 : 0;
-    if (threadIdx.x == 0) {
-        *s.any_active = any;
-        if (s.note) __hip_atomic_store(s.note, 2ull * s.seq + (unsigned long long)any, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
 __global__ __launch_bounds__(NT) void cg_direction_kernel(int n, int w, CgState s) {
     if (*s.any_active == 0) return;
     const int j = blockIdx.y;
@@ -471,6 +508,10 @@ __global__ __launch_bounds__(64) void drift_fin_kernel(int cols, int nchunks, co
     if (threadIdx.x == 0) *out = mx;
 }
 
+// the last-arriving block finishes a CG launch of up to 512 blocks; larger
+// grids (the arrivals on one counter would serialise) take a separate launch
+static int fuse_fin(int nch, int w) { return nch * w <= 512 ? 1 : 0; }
+
 static int cg_chunks(int n, int w, const CgState& s) {
     int nch = chunks_for(n, w);
     while ((size_t)nch * w > s.part_elems && nch > 1) nch /= 2;
@@ -479,14 +520,16 @@ static int cg_chunks(int n, int w, const CgState& s) {
 
 hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb, double tol) {
     const int nch = cg_chunks(n, w, s);
-    hipLaunchKernelGGL(cg_init_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, B, ldb, tol);
-    hipLaunchKernelGGL(cg_init_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
+    const int fin = fuse_fin(nch, w);
+    hipLaunchKernelGGL(cg_init_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, B, ldb, tol, fin);
+    if (!fin) hipLaunchKernelGGL(cg_init_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
     const int nch = cg_chunks(n, w, s);
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s);
-    hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
+    const int fin = fuse_fin(nch, w);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, fin);
+    if (!fin) hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
     return hipGetLastError();
 }
 hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s) {
@@ -496,14 +539,16 @@ hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, c
 hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
                            double tol) {
     const int nch = cg_chunks(n, w, s);
-    hipLaunchKernelGGL(cg_update_tiles_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, ntiles, pq, s, tol);
-    hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
+    const int fin = fuse_fin(nch, w);
+    hipLaunchKernelGGL(cg_update_tiles_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, ntiles, pq, s, tol, fin);
+    if (!fin) hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol) {
     const int nch = cg_chunks(n, w, s);
-    hipLaunchKernelGGL(cg_update_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, tol);
-    hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
+    const int fin = fuse_fin(nch, w);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, s, tol, fin);
+    if (!fin) hipLaunchKernelGGL(cg_update_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s, tol);
     return hipGetLastError();
 }
 hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s) {
