@@ -213,13 +213,15 @@ __global__ __launch_bounds__(64) void apply_stream_kernel(int m, int p, const do
 // Low-rank M apply, first pass: T = L^T Y for L (n x r, r <= 256, ld even,
 // 16-byte aligned) and Y (n x w, w <= 32, ld even).  Workgroup g reduces rows
 // [g * chunk, (g + 1) * chunk); wavefront v owns L's columns [64 v, 64 v + 64)
-// (four 16-column fragments) and all 32 columns of Y (two fragments).  A lane
-// reads two consecutive rows of one column (16 bytes); the .x and .y halves
-// feed two MFMA k-steps, so a step of 8 rows is 16 v_mfma_f64_16x16x4_f64.
-// Partial T tiles are written in lane order and summed in a fixed order by
-// lty_reduce_kernel, which writes T k-major (r x 32) for the second pass.
+// (four 16-column fragments) and all 32 columns of Y (two fragments).  The
+// rows are taken in units of 16: lane group kq = l / 16 reads rows
+// 4 kq .. 4 kq + 3 of its column (two 16-byte loads, 128 contiguous bytes per
+// column and unit over the four groups) and feeds them to four MFMA k-steps,
+// so a unit is 32 v_mfma_f64_16x16x4_f64.  Partial T tiles are written in
+// lane order and summed in a fixed order by lty_reduce_kernel, which writes T
+// k-major (r x 32) for the second pass.
 // ---------------------------------------------------------------------------
-constexpr int LPF = 2;   // 8-row steps per prefetch half
+constexpr int LU = 16;   // rows per unit
 
 __global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, const double* __restrict__ L,
                                                           int64_t ldl, const double* __restrict__ Y, int64_t ldy,
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, c
     const int c = lane % 16, kq = lane / 16;
     const int i_begin = blockIdx.x * chunk;
     const int i_end = min(n, i_begin + chunk);
-    const int nfull = max(0, (i_end - i_begin) / 8);
+    const int nfull = max(0, (i_end - i_begin) / LU);
     d4 acc[4][2];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
@@ -247,70 +249,77 @@ __global__ __launch_bounds__(256) void lowrank_lty_kernel(int n, int r, int w, c
     const bool yok0 = yc0 < w, yok1 = yc1 < w;
     const double* lp[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) lp[t] = L + (int64_t)lc[t] * ldl + i_begin + 2 * kq;
-    const double* yp0 = Y + (int64_t)(yok0 ? yc0 : 0) * ldy + i_begin + 2 * kq;
-    const double* yp1 = Y + (int64_t)(yok1 ? yc1 : 0) * ldy + i_begin + 2 * kq;
+    for (int t = 0; t < 4; ++t) lp[t] = L + (int64_t)lc[t] * ldl + i_begin + 4 * kq;
+    const double* yp0 = Y + (int64_t)(yok0 ? yc0 : 0) * ldy + i_begin + 4 * kq;
+    const double* yp1 = Y + (int64_t)(yok1 ? yc1 : 0) * ldy + i_begin + 4 * kq;
+    // four k-steps of one unit: step e pairs row 4 kq + e of L and Y
+    auto compute = [&](const double2 (&a)[4][2], const double2 (&b)[2][2]) {
+        double2 bb[2][2], aa[4][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bb[0][h] = yok0 ? b[0][h] : double2{0.0, 0.0};
+            bb[1][h] = yok1 ? b[1][h] : double2{0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) aa[t][h] = lok[t] ? a[t][h] : double2{0.0, 0.0};
+        }
+        // all eight accumulators once per k-step, so that no MFMA waits on
+        // the one just issued
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t][h].x, bb[u][h].x, acc[t][u], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t][h].y, bb[u][h].y, acc[t][u], 0, 0, 0);
+        }
+    };
     if (nfull > 0) {
-        double2 a0[LPF][4], b0[LPF][2], a1[LPF][4], b1[LPF][2];
-        auto load = [&](double2 (&a)[LPF][4], double2 (&b)[LPF][2], int s0) {
+        double2 a0[4][2], b0[2][2], a1[4][2], b1[2][2];
+        // surplus loads re-read the last unit (in range) and are not used
+        auto load = [&](double2 (&a)[4][2], double2 (&b)[2][2], int s) {
+            const int64_t o = (int64_t)min(s, nfull - 1) * LU;
 #pragma unroll
-            for (int j = 0; j < LPF; ++j) {
-                const int64_t o = (int64_t)min(s0 + j, nfull - 1) * 8;
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) a[j][t] = *reinterpret_cast<const double2*>(lp[t] + o);
-                b[j][0] = *reinterpret_cast<const double2*>(yp0 + o);
-                b[j][1] = *reinterpret_cast<const double2*>(yp1 + o);
-            }
-        };
-        auto compute = [&](const double2 (&a)[LPF][4], const double2 (&b)[LPF][2], int s0) {
-#pragma unroll
-            for (int j = 0; j < LPF; ++j) {
-                const bool live = s0 + j < nfull;
-                double2 bb[2], aa[4];
-                bb[0] = (live && yok0) ? b[j][0] : double2{0.0, 0.0};
-                bb[1] = (live && yok1) ? b[j][1] : double2{0.0, 0.0};
-#pragma unroll
-                for (int t = 0; t < 4; ++t) aa[t] = lok[t] ? a[j][t] : double2{0.0, 0.0};
-                // all eight accumulators once per k-step, so that no MFMA waits
-                // on the one just issued
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t].x, bb[u].x, acc[t][u], 0, 0, 0);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[t].y, bb[u].y, acc[t][u], 0, 0, 0);
+                for (int t = 0; t < 4; ++t) a[t][h] = *reinterpret_cast<const double2*>(lp[t] + o + 2 * h);
+                b[0][h] = *reinterpret_cast<const double2*>(yp0 + o + 2 * h);
+                b[1][h] = *reinterpret_cast<const double2*>(yp1 + o + 2 * h);
             }
         };
         load(a0, b0, 0);
-        for (int s2 = 0; s2 < nfull; s2 += 2 * LPF) {
-            load(a1, b1, s2 + LPF);
-            compute(a0, b0, s2);
-            load(a0, b0, s2 + 2 * LPF);
-            compute(a1, b1, s2 + LPF);
+        for (int s = 0; s < nfull; s += 2) {
+            load(a1, b1, s + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(a0, b0, s + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            if (s + 1 < nfull) compute(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // rows left over after the full 8-row steps (per-lane guards)
-    for (int i0 = i_begin + 8 * nfull; i0 < i_end; i0 += 8) {
-        const int ia = i0 + 2 * kq, ib = ia + 1;
-        double2 bb[2];
-        bb[0] = double2{(yok0 && ia < i_end) ? Y[(int64_t)yc0 * ldy + ia] : 0.0,
-                        (yok0 && ib < i_end) ? Y[(int64_t)yc0 * ldy + ib] : 0.0};
-        bb[1] = double2{(yok1 && ia < i_end) ? Y[(int64_t)yc1 * ldy + ia] : 0.0,
-                        (yok1 && ib < i_end) ? Y[(int64_t)yc1 * ldy + ib] : 0.0};
+    if (i_begin + LU * nfull < i_end) {
+        // last partial unit of the chunk: rows at or beyond i_end count zero
+        const int i0 = i_begin + LU * nfull;
+        double2 a[4][2], b[2][2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double2 aa = {(lok[t] && ia < i_end) ? L[(int64_t)lc[t] * ldl + ia] : 0.0,
-                                (lok[t] && ib < i_end) ? L[(int64_t)lc[t] * ldl + ib] : 0.0};
+        for (int h = 0; h < 2; ++h) {
+            const int ia = i0 + 4 * kq + 2 * h, ib = ia + 1;
+            b[0][h] = double2{(yok0 && ia < i_end) ? Y[(int64_t)yc0 * ldy + ia] : 0.0,
+                              (yok0 && ib < i_end) ? Y[(int64_t)yc0 * ldy + ib] : 0.0};
+            b[1][h] = double2{(yok1 && ia < i_end) ? Y[(int64_t)yc1 * ldy + ia] : 0.0,
+                              (yok1 && ib < i_end) ? Y[(int64_t)yc1 * ldy + ib] : 0.0};
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.x, bb[u].x, acc[t][u], 0, 0, 0);
-                acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa.y, bb[u].y, acc[t][u], 0, 0, 0);
-            }
+            for (int t = 0; t < 4; ++t)
+                a[t][h] = double2{(lok[t] && ia < i_end) ? L[(int64_t)lc[t] * ldl + ia] : 0.0,
+                                  (lok[t] && ib < i_end) ? L[(int64_t)lc[t] * ldl + ib] : 0.0};
         }
+        compute(a, b);
     }
     double* out = part + ((int64_t)blockIdx.x * 256 + threadIdx.x) * 32;
 #pragma unroll
@@ -491,7 +500,7 @@ hipError_t lowrank_apply_M(hipStream_t st, int n, int r, int w, const double* de
     // first pass: up to two workgroups per CU, chunks of whole prefetch rounds
     int nchunk = std::max(1, std::min(512, n / 512));
     int chunk = (n + nchunk - 1) / nchunk;
-    chunk = ((chunk + 8 * 2 * LPF - 1) / (8 * 2 * LPF)) * (8 * 2 * LPF);
+    chunk = ((chunk + 2 * LU - 1) / (2 * LU)) * (2 * LU);
     nchunk = (n + chunk - 1) / chunk;
     double* Pt = work;                        // r x 32
     double* part = work + 256 * 32;           // nchunk x 8192

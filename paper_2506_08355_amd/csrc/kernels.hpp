@@ -132,6 +132,9 @@ hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const doubl
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
 // p = r + beta p for active columns
 hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s);
+// Bx = I - (G - I)^T / 2, By = I - (G - I) / 2 for G = X^T Y (c x c): the
+// first-order correction (X Bx)^T (Y By) = I + O(|G - I|^2)
+hipError_t biorth_fix_coef(hipStream_t st, int c, const double* G, int64_t ldg, double* Bx, double* By, int64_t ldb);
 
 // Right-hand sides of the block Gauss-Seidel sweep (equation for the sweep):
 //   out[:, j] = lam[j] * (S[:, j] + T[:, g_j]) - U[:, g_j]

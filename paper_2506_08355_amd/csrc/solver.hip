@@ -685,6 +685,21 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     double me = 0;
     for (double e : epsc) me = std::max(me, e);
     stats.max_eps = me;
+    if (c > 0 && c <= kMaxD) {
+        // The returned pairs were locked from bases biorthogonal to the
+        // restore threshold; a first-order correction brings X^T Y = I to
+        // rounding level (each vector moves by O(|X^T Y - I|), far below the
+        // residual tolerance).
+        const int64_t ldg = 2 * kMaxD;
+        CR(gram(segs({{Xc.p, n, c}}), segs({{Yc.p, n, c}}), G, ldg, 0));
+        CK(biorth_fix_coef(st, c, G, ldg, Acoef, Bcoef, kMaxD));
+        const Seg A2[2] = {{Xc.p, n, c}, {Yc.p, n, c}};
+        const double* B2[2] = {Acoef, Bcoef};
+        double* C2[2] = {tX.p, tY.p};
+        CK(gemm_nn_batch(st, (int)n, c, c, 2, A2, B2, kMaxD, C2, n, 1.0, 0.0));
+        CK(copy_cols(st, (int)n, c, tX.p, n, Xc.p, n));
+        CK(copy_cols(st, (int)n, c, tY.p, n, Yc.p, n));
+    }
     if (c > 0) {
         double* OX = op->null_on_M() ? Yc.p : Xc.p;
         double* OY = op->null_on_M() ? Xc.p : Yc.p;

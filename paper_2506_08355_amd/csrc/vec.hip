@@ -314,6 +314,20 @@ __global__ __launch_bounds__(NT) void cg_direction_kernel(int n, int w, CgState 
         s.P[off + i] = s.R[off + i] + b * s.P[off + i];
 }
 
+// Coefficients of the first-order biorthogonality correction of returned
+// pairs: with G = X^T Y (c x c, ld ldg), Bx = I - (G - I)^T / 2 and
+// By = I - (G - I) / 2, so that (X Bx)^T (Y By) = I + O(|G - I|^2).
+__global__ __launch_bounds__(NT) void biorth_fix_kernel(int c, const double* __restrict__ G, int64_t ldg,
+                                                        double* __restrict__ Bx, double* __restrict__ By,
+                                                        int64_t ldb) {
+    for (int idx = blockIdx.x * NT + threadIdx.x; idx < c * c; idx += gridDim.x * NT) {
+        const int i = idx % c, j = idx / c;
+        const double d = (i == j) ? 1.0 : 0.0;
+        Bx[(int64_t)j * ldb + i] = d - 0.5 * (G[(int64_t)i * ldg + j] - d);
+        By[(int64_t)j * ldb + i] = d - 0.5 * (G[(int64_t)j * ldg + i] - d);
+    }
+}
+
 __global__ __launch_bounds__(NT) void gs_rhs_kernel(int n, const double* __restrict__ S, int64_t lds,
                                                     const double* __restrict__ T, const double* __restrict__ U,
                                                     int64_t ldt, const int* __restrict__ win,
@@ -553,6 +567,12 @@ hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol)
 }
 hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s) {
     hipLaunchKernelGGL(cg_direction_kernel, grid_rows(n, w, 256), dim3(NT), 0, st, n, w, s);
+    return hipGetLastError();
+}
+
+hipError_t biorth_fix_coef(hipStream_t st, int c, const double* G, int64_t ldg, double* Bx, double* By, int64_t ldb) {
+    if (c <= 0) return hipSuccess;
+    hipLaunchKernelGGL(biorth_fix_kernel, dim3((c * c + NT - 1) / NT), dim3(NT), 0, st, c, G, ldg, Bx, By, ldb);
     return hipGetLastError();
 }
 
