@@ -98,6 +98,27 @@ def copy_calibration(mib):
                       "correct": ok}), flush=True)
 
 
+def hbm_probe(mib):
+    """The HBM read rate the hardware reaches with the library's plain
+    streaming read kernel over `mib` MiB (20 launches back to back, timed
+    with HIP events on the library's stream); prints one JSON line."""
+    import torch
+    import paper_2506_08355_amd as L
+    count = mib * (1 << 20) // 8
+    src = torch.ones(count, dtype=torch.float64, device="cuda:0")
+    ctx = L.lrep_init(0)
+    res = {"probe": "hbm_read", "bytes": count * 8, "launches": 20}
+    for blocks in (1024, 2048, 4096):
+        out = torch.empty(blocks, dtype=torch.float64, device="cuda:0")
+        L.lrep_test_read(ctx, src, out)
+        ok = abs(float(out.sum()) - count) <= 1e-9 * count
+        ms = L.lrep_test_read(ctx, src, out, iters=20)
+        res[f"read_GBps_{blocks}_blocks"] = round(count * 8 * 20 / (ms * 1e-3) / 1e9, 1)
+        res[f"read_ok_{blocks}"] = ok
+    L.lrep_finalize(ctx)
+    print(json.dumps(res), flush=True)
+
+
 def serve(args, np, torch, gen, L):
     """Serving workload (continuous admission through lrep_submit/lrep_poll):
     a pool of dense and low-rank operators, requests of random nev drawn 50/50
@@ -216,7 +237,12 @@ def main():
                          "(lets profiler passes skip the device QR of the generator)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--hbm-probe", type=int, default=0, metavar="MIB",
+                    help="only time the library's plain streaming read kernel over MIB MiB and exit")
     args = ap.parse_args()
+    if args.hbm_probe:
+        hbm_probe(args.hbm_probe)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -293,6 +319,7 @@ def main():
     prof_launches = 0
     phase_ms = [0.0] * 5
     iters = 0
+    restores = 0
     t_start = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
@@ -305,7 +332,8 @@ def main():
         for k in range(5):
             phase_ms[k] += st.phase_ms[k]
         iters = st.iterations
-        print(f"[bench] step {i}: {lat[-1]:.1f} ms, {st.iterations} iterations, "
+        restores = st.rebiorth
+        print(f"[bench] step {i}: {lat[-1]:.1f} ms, {st.iterations} iterations, {st.rebiorth} restores, "
               f"applies K/M {st.applies_K}/{st.applies_M}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
@@ -388,7 +416,7 @@ def main():
         "config": {"workload": describe(w), "n": n, "nev": nev, "block": block, "window": window, "tol": tol,
                    "seed": w["seed"], "parallelism": "single GPU"},
         "p50_ms": round(lat_s[len(lat_s) // 2], 3), "p99_ms": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 3),
-        "iterations": iters, "max_residual_Hnorm": max_res, "biorth": biorth,
+        "iterations": iters, "biorth_restores": restores, "max_residual_Hnorm": max_res, "biorth": biorth,
         "phase_ms_per_solve": dict(zip(["init", "small_problem", "convergence_check", "pq", "wz"],
                                        [round(v / args.steps, 2) for v in phase_ms])),
         "roofline": roofline, "cpu_baseline": cpu,

@@ -53,6 +53,14 @@ int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, i
 int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint16_t* A16, const double* X,
                       const double* rr, double* Y);
 
+/* out[b] = sum of block b's grid-stride share of src[0:count] (device FP64,
+ * 16-byte aligned, count even; out holds `blocks` doubles), `iters` launches
+ * back to back on the context's stream, *ms = their total time from HIP
+ * events on that stream: a plain streaming read, the reference for the HBM
+ * read rate the hardware reaches. */
+int lrep_test_read(lrep_ctx_t ctx, const double* src, int64_t count, int blocks, int iters, double* out,
+                   double* ms);
+
 /* dst[0:count] = src[0:count] (device FP64 arrays, 16-byte aligned): a
  * plain streaming copy of known size, the reference against which hardware
  * byte counters (FETCH_SIZE, WRITE_SIZE) are scaled. */

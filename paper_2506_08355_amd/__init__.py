@@ -138,6 +138,7 @@ _SIGS = {
     "lrep_test_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "lrep_test_convert16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _I64, _P]),
     "lrep_test_apply16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
+    "lrep_test_read": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double)]),
     "lrep_test_copy": (ctypes.c_int, [_P, _P, _P, _I64]),
 }
 
@@ -395,6 +396,17 @@ def lrep_test_apply16(ctx, precision, A16, X, rr, Y):
     return _check(lib().lrep_test_apply16(ctx, precision, n, cols, ctypes.c_void_p(A16.data_ptr()),
                                           colmajor(X)[0], ctypes.c_void_p(rr.data_ptr()), colmajor(Y)[0]),
                   ctx, "lrep_test_apply16")
+
+
+def lrep_test_read(ctx, src, out, iters=1):
+    """out[b] = block b's share of the sum of the contiguous FP64 device
+    tensor src (a plain streaming read), len(out) blocks, `iters` launches;
+    returns their total time in ms (HIP events on the library's stream)."""
+    _ready(src)
+    ms = ctypes.c_double(0.0)
+    _check(lib().lrep_test_read(ctx, ctypes.c_void_p(src.data_ptr()), src.numel(), out.numel(), iters,
+                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(ms)), ctx, "lrep_test_read")
+    return ms.value
 
 
 def lrep_test_copy(ctx, src, dst):

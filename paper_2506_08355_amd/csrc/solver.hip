@@ -546,6 +546,22 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             --it;
             stats.rebiorth++;
             just_restored = true;
+            if (hs->offmax <= 1e-8) {
+                // small loss: first-order correction with S = U^T V,
+                // U Bx, V By (Bx = I - (S - I)^T / 2, By = I - (S - I) / 2) and
+                // the images with them, so (U Bx)^T (V By) = I + O(|S - I|^2) and
+                // K (U Bx) = (K U) Bx stays exact; the corrected basis is
+                // written to the other buffer set (free until the pull-back of
+                // the redone iteration)
+                CK(biorth_fix_coef(st, d, S, kMaxD, Acoef, Bcoef, kMaxD));
+                const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+                const double* B4[4] = {Acoef, Bcoef, Acoef, Bcoef};
+                double* C4[4] = {NX, NY, NKX, NMY};
+                CK(gemm_nn_batch(st, (int)n, d, d, 4, A4, B4, kMaxD, C4, n, 1.0, 0.0));
+                cur = nxt;
+                off = 0;
+                continue;
+            }
             need_fresh = true;
             CR(block_mgs(U, V, d, U, V, &kept));
             d = kept;

@@ -18,6 +18,26 @@ __global__ __launch_bounds__(256) void copy_kernel(const double2* __restrict__ s
         dst[i] = src[i];
 }
 
+// plain streaming read: out[block] = sum of the block's grid-stride share of
+// src (16-byte loads), the reference for the achievable HBM read rate
+__global__ __launch_bounds__(256) void read_sum_kernel(const double2* __restrict__ src, int64_t pairs,
+                                                       double* __restrict__ out) {
+    __shared__ double red[256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * 256) {
+        const double2 v = src[i];
+        s0 += v.x;
+        s1 += v.y;
+    }
+    red[threadIdx.x] = s0 + s1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 int finish(Ctx* c, hipError_t e) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -119,6 +139,31 @@ int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint
     if (e == hipSuccess)
         e = cg_dense_apply16(ctx->stream, precision, n, cols, A16, const_cast<double*>(X), nullptr, nullptr, nullptr,
                              rr, 1, Y, pq.p, work.p, welems, reinterpret_cast<const int*>(flag.p), nullptr, nullptr);
+    return finish(ctx, e);
+}
+
+int lrep_test_read(lrep_ctx_t ctx, const double* src, int64_t count, int blocks, int iters, double* out,
+                   double* ms) {
+    if (!ctx || !src || !out || !ms || count < 0 || (count & 1) || blocks < 1 || blocks > 65536 || iters < 1 ||
+        (reinterpret_cast<uintptr_t>(src) & 15))
+        return LREP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) {
+        hipLaunchKernelGGL(read_sum_kernel, dim3(blocks), dim3(256), 0, ctx->stream,
+                           reinterpret_cast<const double2*>(src), count / 2, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    *ms = (double)t;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     return finish(ctx, e);
 }
 
