@@ -622,13 +622,19 @@ __global__ __launch_bounds__(256) void small_mgs_kernel(int d, int nw, const dou
                                                         const double* __restrict__ n0, double* __restrict__ Ph,
                                                         double* __restrict__ Qh, int* __restrict__ status,
                                                         double cos_tol, double dep_tol) {
+    // d <= kMaxD = 128: a wavefront covers a column with two entries per lane.
+    // Every wavefront forms the pivot quantities of column l itself (same
+    // data, same order: bitwise the same decisions everywhere, no barrier),
+    // the wavefronts then update the later columns they own, and one barrier
+    // per kept column orders that against the next pivot.  Column l stays
+    // unscaled in LDS (later steps never read it); its scaled form goes to
+    // Ph, Qh.
     __shared__ double P[kMaxD * 64];
     __shared__ double Q[kMaxD * 64];
-    __shared__ double xn[64], yn[64], rr[64], ss[64];
+    __shared__ double xn[64], yn[64];
     __shared__ int live[64];
-    __shared__ double red[256 / WAVE];
-    __shared__ double sc[4];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid % WAVE, wid = tid / WAVE;
+    constexpr int NWV = 256 / WAVE;
     for (int idx = tid; idx < d * nw; idx += nt) {
         const int i = idx % d, j = idx / d;
         P[j * kMaxD + i] = Vin[(int64_t)j * kMaxD + i];
@@ -636,7 +642,7 @@ __global__ __launch_bounds__(256) void small_mgs_kernel(int d, int nw, const dou
     }
     __syncthreads();
     // column norms of the projected inputs (x_l, y_l of the MGS) and liveness
-    for (int j = wid; j < nw; j += nt / WAVE) {
+    for (int j = wid; j < nw; j += NWV) {
         double a = 0, b = 0;
         for (int i = lane; i < d; i += WAVE) {
             a += P[j * kMaxD + i] * P[j * kMaxD + i];
@@ -651,56 +657,53 @@ __global__ __launch_bounds__(256) void small_mgs_kernel(int d, int nw, const dou
         }
     }
     __syncthreads();
+    const int i0 = lane, i1 = lane + WAVE;
     int np = 0;
     for (int l = 0; l < nw; ++l) {
         if (!live[l]) continue;
         const double* p = P + l * kMaxD;
         const double* q = Q + l * kMaxD;
-        double eta = 0, pn = 0, qn = 0;
-        for (int i = tid; i < d; i += nt) {
-            eta += p[i] * q[i];
-            pn += p[i] * p[i];
-            qn += q[i] * q[i];
-        }
-        eta = block_sum<256>(eta, red);
-        pn = sqrt(block_sum<256>(pn, red));
-        qn = sqrt(block_sum<256>(qn, red));
+        const double p0 = i0 < d ? p[i0] : 0.0, p1 = i1 < d ? p[i1] : 0.0;
+        const double q0 = i0 < d ? q[i0] : 0.0, q1 = i1 < d ? q[i1] : 0.0;
+        const double eta = wsum(p0 * q0 + p1 * q1);
+        const double pn = sqrt(wsum(p0 * p0 + p1 * p1));
+        const double qn = sqrt(wsum(q0 * q0 + q1 * q1));
         if (eta == 0.0 || fabs(eta) <= cos_tol * pn * qn || pn <= dep_tol * xn[l] || qn <= dep_tol * yn[l]) continue;
         const double sl = sqrt(fabs(eta));
         const double rl = eta < 0 ? -sl : sl;
-        for (int i = tid; i < d; i += nt) {
-            const double pv = p[i] / rl, qv = q[i] / sl;
-            P[l * kMaxD + i] = pv;
-            Q[l * kMaxD + i] = qv;
-            Ph[(int64_t)np * kMaxD + i] = pv;
-            Qh[(int64_t)np * kMaxD + i] = qv;
+        const double irl = 1.0 / rl, isl = 1.0 / sl;
+        const double pv0 = p0 * irl, pv1 = p1 * irl, qv0 = q0 * isl, qv1 = q1 * isl;
+        if (wid == (l % NWV)) {
+            if (i0 < d) {
+                Ph[(int64_t)np * kMaxD + i0] = pv0;
+                Qh[(int64_t)np * kMaxD + i0] = qv0;
+            }
+            if (i1 < d) {
+                Ph[(int64_t)np * kMaxD + i1] = pv1;
+                Qh[(int64_t)np * kMaxD + i1] = qv1;
+            }
+        }
+        // later columns: r_j = q_l . p_j, p_j -= r_j p_l; s_j = p_l . q_j, q_j -= s_j q_l
+        for (int j = l + 1 + wid; j < nw; j += NWV) {
+            double* pj = P + j * kMaxD;
+            double* qj = Q + j * kMaxD;
+            const double a0 = i0 < d ? pj[i0] : 0.0, a1 = i1 < d ? pj[i1] : 0.0;
+            const double b0 = i0 < d ? qj[i0] : 0.0, b1 = i1 < d ? qj[i1] : 0.0;
+            const double r = wsum(qv0 * a0 + qv1 * a1);
+            const double sj = wsum(pv0 * b0 + pv1 * b1);
+            if (i0 < d) {
+                pj[i0] = a0 - r * pv0;
+                qj[i0] = b0 - sj * qv0;
+            }
+            if (i1 < d) {
+                pj[i1] = a1 - r * pv1;
+                qj[i1] = b1 - sj * qv1;
+            }
         }
         ++np;
         __syncthreads();
-        // coefficients for every later column: r_j = q_l . p_j, s_j = p_l . q_j
-        for (int j = l + 1 + wid; j < nw; j += nt / WAVE) {
-            double r = 0, s = 0;
-            for (int i = lane; i < d; i += WAVE) {
-                r += q[i] * P[j * kMaxD + i];
-                s += p[i] * Q[j * kMaxD + i];
-            }
-            r = wsum(r);
-            s = wsum(s);
-            if (lane == 0) {
-                rr[j] = r;
-                ss[j] = s;
-            }
-        }
-        __syncthreads();
-        for (int idx = tid; idx < d * (nw - l - 1); idx += nt) {
-            const int i = idx % d, j = l + 1 + idx / d;
-            P[j * kMaxD + i] -= rr[j] * p[i];
-            Q[j * kMaxD + i] -= ss[j] * q[i];
-        }
-        __syncthreads();
     }
     if (tid == 0) status[ST_NP] = np;
-    (void)sc;
 }
 
 // ---------------------------------------------------------------------------
