@@ -247,7 +247,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs the solver on a single MI355X; "
+        print("bench.py measures one GPU: the solver runs on a single MI355X; "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
