@@ -124,19 +124,24 @@ def serve(args, np, torch, gen, L):
     a pool of dense and low-rank operators, requests of random nev drawn 50/50
     over them, first all at once (closed-loop solve rate), then with Poisson
     arrivals at rho times that rate; latency = submit to completed poll.
-    Sizes are the serving configuration's ranges capped (dense n <= 8192,
-    low-rank n <= 32768) so that a run stays within a few minutes."""
+    `--serve-sizes full` draws the serving configuration's ranges (dense n
+    in [512, 16384], low-rank n in [16384, 262144]); the default caps them
+    (dense n <= 8192, low-rank n <= 32768) so that a run stays within a few
+    minutes.  `--budget-gib` caps the context's HBM (requests then queue for
+    memory)."""
     rng = np.random.default_rng(1005)
     dev = torch.device("cuda:0")
-    ctx = L.lrep_init(0)
+    full = args.serve_sizes == "full"
+    dmax, lmax = (16384, 262144) if full else (8192, 32768)
+    ctx = L.lrep_init(0, int(args.budget_gib * (1 << 30)))
     pool, t0 = [], time.time()
-    for i in range(6):       # dense, n log-uniform [512, 8192], multiple of 64
-        n = int(64 * round(np.exp(rng.uniform(np.log(512), np.log(8192))) / 64))
+    for i in range(6):       # dense, n log-uniform [512, dmax], multiple of 64
+        n = int(64 * round(np.exp(rng.uniform(np.log(512), np.log(dmax))) / 64))
         Kd, Md, _, _ = gen.dense_operator_device(n, 2000 + i, dev)
         pool.append((L.lrep_create_dense(ctx, Kd.T, Md.T), n))
         del Kd, Md
-    for i in range(6):       # low rank, n log-uniform [16384, 32768], rank uniform {64..256}
-        n = int(64 * round(np.exp(rng.uniform(np.log(16384), np.log(32768))) / 64))
+    for i in range(6):       # low rank, n log-uniform [16384, lmax], rank uniform {64..256}
+        n = int(64 * round(np.exp(rng.uniform(np.log(16384), np.log(lmax))) / 64))
         r = int(rng.integers(64, 257))
         f = gen.casida_factors(n, r, 3000 + i)
         pool.append((L.lrep_create_lowrank(ctx, torch.from_numpy(f.delta).to(dev),
@@ -198,10 +203,12 @@ def serve(args, np, torch, gen, L):
         "value": round(len(reqs) / open_time, 3), "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
         "warmup": 0, "ms_per_step": round(open_time * 1e3 / len(reqs), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "serving: 6 dense (n log-uniform 512-8192) + 6 low-rank (n log-uniform "
-                               "16384-32768, rank 64-256) operators, requests 50/50, nev uniform 4-64, tol 1e-8, "
+        "config": {"workload": f"serving: 6 dense (n log-uniform 512-{dmax}) + 6 low-rank (n log-uniform "
+                               f"16384-{lmax}, rank 64-256) operators, requests 50/50, nev uniform 4-64, tol 1e-8, "
                                f"Poisson arrivals at rho={args.rho} of the closed-loop rate",
-                   "requests": len(reqs), "workers": 4},
+                   "requests": len(reqs), "workers": 4,
+                   "hbm_budget_gib": args.budget_gib if args.budget_gib else None,
+                   "operator_n": [n for _, n in pool]},
         "closed_loop_solves_per_s": round(rate, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "all_ok": ok, "failed": failed, "slowest": slow,
@@ -228,6 +235,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense8192", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--serve-sizes", choices=["reduced", "full"], default="reduced",
+                    help="serve: operator size ranges (full: dense n <= 16384, low-rank n <= 262144)")
+    ap.add_argument("--budget-gib", type=float, default=0.0, help="serve: HBM budget of the context (0: none)")
     ap.add_argument("--rho", type=float, default=0.7,
                     help="serve: Poisson arrival rate as a fraction of the closed-loop solve rate")
     ap.add_argument("--cpu-iters", type=int, default=40,
