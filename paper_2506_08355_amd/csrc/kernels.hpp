@@ -122,9 +122,7 @@ hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double*
                    double tol);
 // alpha_j = rr_j / (p_j . q_j) for active columns (p.q <= 0 stops the column)
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s);
-// alpha from the per-tile sums written by cg_dense_apply (ntiles x 32)
-hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s);
-// cg_alpha_tiles and cg_update in one launch: every block forms alpha of its
+// alpha from the per-tile sums and cg_update in one launch: every block forms alpha of its
 // column from the tile sums in the same fixed order
 hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
                            double tol);
@@ -167,8 +165,6 @@ hipError_t sign_normalise(hipStream_t st, int n, int cols, double* X, double* Y,
 // K <- A - B, M <- A + B element-wise (K holds A and M holds B on entry), n x n, ld n
 hipError_t combine_ab(hipStream_t st, int64_t n, double* K, double* M);
 
-// zero a column block
-hipError_t zero_cols(hipStream_t st, int n, int cols, double* X, int64_t ld);
 
 // ---- small.hip (small d x d data, d <= 128) ------------------------------
 // Small structured LREP:  K^ = L1 L1^T, M^ = L2 L2^T, SVD of L2^T L1 by

@@ -185,38 +185,6 @@ __global__ __launch_bounds__(NT) void cg_alpha_kernel(int n, int w, int nchunks,
     if (fin && cg_arrive_last(s) && threadIdx.x < 64) cg_alpha_fin_wave(w, nchunks, s);
 }
 
-// alpha_fin on the per-tile p.q sums of the fused dense path: thread
-// (grp, col) sums tiles grp, grp + 32, ... in order, then one thread per
-// column adds the 32 group sums in order.
-__global__ __launch_bounds__(1024) void cg_alpha_tiles_kernel(int w, int ntiles, const double* __restrict__ pq,
-                                                              CgState s) {
-    __shared__ double red[32][33];
-    if (*s.any_active == 0) return;
-    const int col = threadIdx.x % 32, grp = threadIdx.x / 32;
-    double t = 0.0;
-    for (int k = grp; k < ntiles; k += 32) t += pq[(int64_t)k * 32 + col];
-    red[grp][col] = t;
-    __syncthreads();
-    if (threadIdx.x >= 64) return;
-    int na = 0;
-    const int c = threadIdx.x;
-    if (c < w) {
-        double a = 0.0;
-        if (s.active[c]) {
-            ++na;
-            double sum = 0.0;
-            for (int k = 0; k < 32; ++k) sum += red[k][c];
-            if (sum > 0.0)
-                a = s.rr[c] / sum;
-            else
-                s.active[c] = 0;   // breakdown: p^T A p <= 0 (singular operator)
-        }
-        s.alpha[c] = a;
-    }
-    for (int off = 32; off >= 1; off >>= 1) na += __shfl_xor(na, off, 64);
-    if (threadIdx.x == 0) *s.napplies += (unsigned long long)na;
-}
-
 // beta, rr, active and any_active from the per-chunk sums of |r|^2, run by
 // one wavefront (lanes over columns)
 __device__ void cg_fin_wave(int w, int nchunks, const CgState& s, double tol) {
@@ -347,11 +315,6 @@ __global__ __launch_bounds__(NT) void copy_cols_kernel(int n, const double* __re
     const int j = blockIdx.y;
     for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
         out[(int64_t)j * ldo + i] = in[(int64_t)j * ldi + i];
-}
-
-__global__ __launch_bounds__(NT) void zero_cols_kernel(int n, double* __restrict__ X, int64_t ld) {
-    const int j = blockIdx.y;
-    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) X[(int64_t)j * ld + i] = 0.0;
 }
 
 __global__ __launch_bounds__(1024) void max_offidentity_kernel(int d, const double* __restrict__ S, int64_t lds,
@@ -546,10 +509,6 @@ hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
     if (!fin) hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
     return hipGetLastError();
 }
-hipError_t cg_alpha_tiles(hipStream_t st, int w, int ntiles, const double* pq, const CgState& s) {
-    hipLaunchKernelGGL(cg_alpha_tiles_kernel, dim3(1), dim3(1024), 0, st, w, ntiles, pq, s);
-    return hipGetLastError();
-}
 hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
                            double tol) {
     const int nch = cg_chunks(n, w, s);
@@ -594,12 +553,6 @@ hipError_t combine_ab(hipStream_t st, int64_t n, double* K, double* M) {
     const int64_t total = n * n;
     hipLaunchKernelGGL(combine_ab_kernel, dim3((unsigned)std::min<int64_t>(8192, (total + NT - 1) / NT)), dim3(NT), 0,
                        st, total, K, M);
-    return hipGetLastError();
-}
-
-hipError_t zero_cols(hipStream_t st, int n, int cols, double* X, int64_t ld) {
-    if (cols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, X, ld);
     return hipGetLastError();
 }
 
