@@ -180,6 +180,27 @@ int lrep_create_dense(lrep_ctx_t ctx, int64_t n, const double* K, const double* 
 int lrep_create_lowrank(lrep_ctx_t ctx, int64_t n, int64_t rank, const double* delta,
                         const double* L, int64_t ldl, uint32_t flags, lrep_op_t* op);
 
+/* Matrix-free operator: the method touches K and M only through block
+ * products (Section 3.2), so an operator may be supplied as a function
+ *   apply(user, which, cols, X, ldx, Y, ldy, stream)
+ * that makes Y = K X (which = 0) or Y = M X (which = 1) for the device
+ * blocks X (n x cols, leading dimension ldx) and Y (n x cols, ld ldy), with
+ * K and M as in lrep_create_dense (symmetric, M positive definite, or the
+ * roles exchanged with LREP_NULL_ON_M).  The library's work that produces X
+ * is already enqueued on `stream` (a hipStream_t); the function enqueues its
+ * product on that stream, or finishes it before returning, and returns 0
+ * (any other value ends the solve with LREP_EDEVICE).  It is called from
+ * the thread that runs the solve (the caller of lrep_solve, or a serving
+ * worker), from several threads at once when requests of the operator are
+ * served concurrently.  `user` is passed through; the library holds no
+ * device memory for the operator.  Mixed precision (opts.precision) does
+ * not apply to it.
+ * Errors: LREP_EINVAL. */
+typedef int (*lrep_apply_fn)(void* user, int32_t which, int64_t cols, const double* X, int64_t ldx, double* Y,
+                             int64_t ldy, void* stream);
+int lrep_create_callback(lrep_ctx_t ctx, int64_t n, lrep_apply_fn apply, void* user, uint32_t flags,
+                         lrep_op_t* op);
+
 /* Declare the generalized null space (Lemma 2.3, Remark on computing V0):
  * X0 (n x r, ld) spans N(K) (or N(M) with LREP_NULL_ON_M).  The library
  * solves M Y0~ = X0~ by CG on the device, factors X0~^T Y0~ = C^T C and keeps

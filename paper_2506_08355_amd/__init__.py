@@ -119,6 +119,7 @@ _SIGS = {
     "lrep_finalize": (ctypes.c_int, [_P]),
     "lrep_create_dense": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_create_lowrank": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, ctypes.c_uint32, ctypes.POINTER(_P)]),
+    "lrep_create_callback": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_set_nullspace": (ctypes.c_int, [_P, _I64, _P, _I64, _I32]),
     "lrep_destroy_op": (ctypes.c_int, [_P]),
     "lrep_solve": (ctypes.c_int, [_P, _I64, _I64, _I64, _D, ctypes.POINTER(lrep_solve_opts_t), _P, _P, _P, _I64,
@@ -240,6 +241,29 @@ def lrep_create_dense(ctx, K, M, flags: int = 0):
     return op
 
 
+# C type of the operator product callback (lrep_apply_fn)
+APPLY_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p)
+_callbacks = {}   # op handle -> the ctypes callback, kept alive while the operator exists
+
+
+def lrep_create_callback(ctx, n, apply, flags: int = 0):
+    """Matrix-free operator: apply(which, cols, X_ptr, ldx, Y_ptr, ldy, stream)
+    makes Y = K X (which 0) or M X (which 1) on the device (raw pointers,
+    column-major) and returns 0; see lrep_apply_fn in lrep.h."""
+    def tramp(user, which, cols, X, ldx, Y, ldy, stream):
+        try:
+            return int(apply(which, cols, X, ldx, Y, ldy, stream))
+        except Exception:   # an exception must not cross the C boundary
+            return -1
+    cb = APPLY_FN(tramp)
+    op = _P()
+    _check(lib().lrep_create_callback(ctx, n, ctypes.cast(cb, ctypes.c_void_p), None, flags, ctypes.byref(op)), ctx,
+           "lrep_create_callback")
+    _callbacks[op.value] = cb
+    return op
+
+
 def lrep_create_lowrank(ctx, delta, L, flags: int = 0):
     pd, n, dd = colmajor(delta)
     pl, ldl, dl = colmajor(L)
@@ -261,7 +285,9 @@ def lrep_set_nullspace(op, X0, ctx=None):
 
 
 def lrep_destroy_op(op):
-    return _check(lib().lrep_destroy_op(op), what="lrep_destroy_op")
+    rc = _check(lib().lrep_destroy_op(op), what="lrep_destroy_op")
+    _callbacks.pop(op.value if isinstance(op, _P) else op, None)
+    return rc
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,

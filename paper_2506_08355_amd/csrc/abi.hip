@@ -214,6 +214,21 @@ int lrep_create_dense(lrep_ctx_t c, int64_t n, const double* K, const double* M,
     return LREP_OK;
 }
 
+int lrep_create_callback(lrep_ctx_t c, int64_t n, lrep_apply_fn apply, void* user, uint32_t flags,
+                         lrep_op_t* out) {
+    if (!c || !out || !apply || n < 1 || n > (int64_t)INT32_MAX) return LREP_EINVAL;
+    *out = nullptr;
+    auto* op = new lrep_op_s();
+    op->ctx = c;
+    op->n = n;
+    op->kind = 2;
+    op->flags = flags;
+    op->apply_fn = apply;
+    op->apply_user = user;
+    *out = op;
+    return LREP_OK;
+}
+
 int lrep_create_lowrank(lrep_ctx_t c, int64_t n, int64_t rank, const double* delta, const double* L, int64_t ldl,
                         uint32_t flags, lrep_op_t* out) {
     if (!c || !out || !delta || n < 1 || rank < 0 || (rank > 0 && (!L || ldl < n)) || n > (int64_t)INT32_MAX)

@@ -36,7 +36,7 @@ struct DevBuf {
 struct Op {
     Ctx* ctx = nullptr;
     int64_t n = 0;
-    int kind = 0;              // 0 dense, 1 low rank
+    int kind = 0;              // 0 dense, 1 low rank, 2 caller-supplied products
     uint32_t flags = 0;
     // dense
     double* K = nullptr;
@@ -48,6 +48,9 @@ struct Op {
     double* L = nullptr;
     int64_t rank = 0, ldl = 0;
     DevBuf dbuf, Lbuf;
+    // caller-supplied products
+    lrep_apply_fn apply_fn = nullptr;
+    void* apply_user = nullptr;
     // generalized null space, biorthonormal X0^T Y0 = I (roles already exchanged)
     int64_t r0 = 0;
     DevBuf X0, Y0;

@@ -134,6 +134,9 @@ struct Solver {
         } else if (op->kind == 0) {
             prof_b.push_back(8.0 * nn * nn + 16.0 * nn * c);
             prof_f.push_back(2.0 * nn * nn * c);
+        } else if (op->kind == 2) {   // caller-supplied products: no byte model
+            prof_b.push_back(0.0);
+            prof_f.push_back(0.0);
         } else {   // low-rank M: L read twice, Y read twice, result written once
             const double r = (double)op->rank;
             prof_b.push_back(16.0 * nn * r + 24.0 * nn * c);
@@ -317,7 +320,8 @@ struct Solver {
             int* logslot = nullptr;
             // timed: the dense applies, and the low-rank M applies (the K applies of
             // the low-rank operator are a diagonal scaling)
-            const bool timed = o.profile && (op->kind == 0 || ((which == 0) == op->null_on_M()));
+            const bool timed =
+                o.profile && (op->kind == 0 || (op->kind == 1 && ((which == 0) == op->null_on_M())));
             hipEvent_t* ev = timed ? prof_next(nw, Ad ? &logslot : nullptr, A16 ? o.precision : 0) : nullptr;
             if (A16) {
                 CK(cg_dense_apply16(st, o.precision, (int)n, nw, A16, cgP.p, cgR.p, cg_beta, cg_active, cg_rr,
@@ -740,6 +744,14 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
     if (cols <= 0) return LREP_OK;
     const bool useK = (which == 0) != op->null_on_M();
     hipError_t e = hipSuccess;
+    if (op->kind == 2) {
+        const int rc = op->apply_fn(op->apply_user, useK ? 0 : 1, cols, X, ldx, Y, ldy, st);
+        if (rc != 0) {
+            op->ctx->set_error("operator apply callback returned " + std::to_string(rc));
+            return LREP_EDEVICE;
+        }
+        return LREP_OK;
+    }
     if (op->kind == 0) {
         const double* Ad = useK ? op->K : op->M;
         const bool stream_ok = cols <= 32 && (op->ld % 2) == 0 && (reinterpret_cast<uintptr_t>(Ad) % 16) == 0;

@@ -32,6 +32,7 @@ def test_invalid_arguments_are_rejected_without_device_work():
     assert lib.lrep_solve(None, 1, 1, 1, 1e-8, None, None, None, None, 1, None) == L.LREP_EINVAL
     assert lib.lrep_poll(None, 1, None) == L.LREP_EINVAL
     assert lib.lrep_destroy_op(None) == L.LREP_EINVAL
+    assert lib.lrep_create_callback(None, 10, None, None, 0, None) == L.LREP_EINVAL
 
 
 def test_binding_layout_checks():

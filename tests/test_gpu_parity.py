@@ -174,3 +174,53 @@ def test_error_paths(ctx):
     rc, *_ = gpu_solve(ctx, op, n, 4, 4, 1e-8)
     assert rc in (L.LREP_ENUMERIC, L.LREP_ENOTSPD)
     L.lrep_destroy_op(op)
+
+
+@pytest.mark.parametrize("null_on_m", [False, True], ids=["km", "role_swap"])
+def test_callback_operator(ctx, null_on_m):
+    """Matrix-free operator (lrep_create_callback): the products come from a
+    caller function, here one that forwards to a dense operator's apply on
+    the same context (so on the solve's stream).  The solve takes the
+    generic CG path and must reach the oracle's eigenpairs of config 1; with
+    the role flag the function is asked for the exchanged operators."""
+    n, nev, block, tol = 256, 8, 16, 1e-10
+    K, M, f = gen.dense_operator(n, 1001)
+    U, _ = gen.init_block(n, 3 * block, 7)
+    inner = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    calls = {"K": 0, "M": 0}
+
+    def apply(which, cols, X, ldx, Y, ldy, stream):
+        if ldx != n or ldy != n:
+            return 1
+        calls["K" if which == 0 else "M"] += 1
+        return L.lib().lrep_test_apply(inner, which, cols, X, Y)
+
+    # with the role flag the library exchanges the roles inside and back on
+    # return: the function still sees which = 0 as K, and X, Y come back in
+    # the caller's roles
+    flags = L.LREP_NULL_ON_M if null_on_m else 0
+    op = L.lrep_create_callback(ctx, n, apply, flags)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U)
+    L.lrep_destroy_op(op)
+    L.lrep_destroy_op(inner)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    assert calls["K"] > 0 and calls["M"] > 0
+    ref_lam = exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev)
+    check_pair(lam, X, Y, ref_lam, lambda v: K @ v, lambda v: M @ v, f.norm_H())
+    assert st.n_converged == nev
+
+
+def test_callback_error_ends_solve(ctx):
+    """A product function that reports failure ends the solve with
+    LREP_EDEVICE and a message naming the callback (no device fault)."""
+    n = 256
+
+    def apply(which, cols, X, ldx, Y, ldy, stream):
+        return 7
+
+    op = L.lrep_create_callback(ctx, n, apply)
+    U, _ = gen.init_block(n, 48, 7)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, 8, 16, 1e-10, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_EDEVICE
+    assert "callback" in L.lrep_last_error(ctx)
