@@ -380,8 +380,8 @@ def main():
             kname = "apply_stream_kernel (CG block apply, w=%d)" % window
             abytes = 8.0 * n * n + 16.0 * n * window
         else:
-            kname = ("lowrank_lty_kernel + lty_reduce_kernel + apply_stream_kernel "
-                     "(low-rank M apply of the CG, w=%d, both passes)" % window)
+            kname = ("lr_lty_kernel + lr_reduce_kernel + lr_apply_kernel "
+                     "(low-rank M apply of the CG on the row-major copy of L, w=%d, both passes)" % window)
             abytes = 16.0 * n * w["rank"] + 24.0 * n * window
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

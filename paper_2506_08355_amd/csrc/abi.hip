@@ -268,6 +268,19 @@ int lrep_create_lowrank(lrep_ctx_t c, int64_t n, int64_t rank, const double* del
             return LREP_EDEVICE;
         }
     }
+    // row-major copy of L for the streaming M apply (when the HBM budget
+    // allows it; without it the column-major passes are used)
+    if (rank >= 1 && rank <= 256 &&
+        op->Lrbuf.alloc(c, (size_t)n * lowrank_row_ld(rank) * sizeof(double)) == LREP_OK) {
+        hipError_t e = lowrank_make_rows(c->stream, (int)n, (int)rank, op->L, op->ldl, op->Lrbuf.p);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->set_error(hipGetErrorString(e));
+            delete op;
+            return LREP_EDEVICE;
+        }
+        op->Lr = op->Lrbuf.p;
+    }
     *out = op;
     return LREP_OK;
 }

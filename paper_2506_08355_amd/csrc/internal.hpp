@@ -48,6 +48,9 @@ struct Op {
     double* L = nullptr;
     int64_t rank = 0, ldl = 0;
     DevBuf dbuf, Lbuf;
+    // row-major copy of L (n x lowrank_row_ld(rank)) for the streaming M apply
+    DevBuf Lrbuf;
+    double* Lr = nullptr;
     // caller-supplied products
     lrep_apply_fn apply_fn = nullptr;
     void* apply_user = nullptr;

@@ -88,6 +88,17 @@ hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t
                           double* Q, double* pq, double* work, size_t work_elems,
                           const int* any_active, hipEvent_t* ev = nullptr, int* flag_log = nullptr);
 
+// ---- lowrank.hip ---------------------------------------------------------
+// leading dimension of the row-major copy of L (rank rounded up to 64)
+int64_t lowrank_row_ld(int64_t r);
+// Lr (n x lowrank_row_ld(r), row-major, zero-padded) = L (n x r, ld ldl), r <= 256
+hipError_t lowrank_make_rows(hipStream_t st, int n, int r, const double* L, int64_t ldl, double* Lr);
+// C = delta o Y + 2 L (L^T Y) from the row-major copy, w <= 32 columns of Y
+// (ld even, 16-byte aligned); `work` holds 256 * 32 + nchunk * 8192 doubles
+hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
+                                const double* Y, int64_t ldy, double* C, int64_t ldc, double* work,
+                                size_t work_elems, const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
+
 // ---- vec.hip -------------------------------------------------------------
 // Y[:, j] = delta o X[:, j]
 hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta,

@@ -765,6 +765,14 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
         }
     } else if (useK) {
         e = diag_scale(st, (int)op->n, cols, op->delta, X, ldx, Y, ldy, active_flag);
+    } else if (op->Lr && (ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) {
+        // streaming low-rank apply on the row-major copy, 32 columns at a time
+        for (int c0 = 0; c0 < cols && e == hipSuccess; c0 += 32) {
+            const int w = std::min(32, cols - c0);
+            e = lowrank_apply_M_rows(st, (int)op->n, (int)op->rank, w, op->delta, op->Lr, X + (size_t)c0 * ldx, ldx,
+                                     Y + (size_t)c0 * ldy, ldy, work, work_elems, active_flag,
+                                     c0 == 0 ? ev : nullptr);
+        }
     } else if (op->rank <= 256 && (op->ldl % 2) == 0 && (ldx % 2) == 0 &&
                (reinterpret_cast<uintptr_t>(op->L) % 16) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) {
         // streaming low-rank apply, 32 columns at a time
