@@ -105,8 +105,11 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
 int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);
 
 // Operator apply with the roles (after a possible exchange): which = 0 -> "K", 1 -> "M".
+// With pq (low-rank operators, cols <= 32, op_apply_has_pq true), also
+// pq[t * 32 + j] = the sum over the 64-row tile t of X[:, j] Y[:, j].
 int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy,
              double* work, size_t work_elems, double* small, const int* active_flag,
-             hipEvent_t* ev = nullptr);
+             hipEvent_t* ev = nullptr, double* pq = nullptr);
+bool op_apply_has_pq(const Op* op, int which, const double* X, int64_t ldx, int cols);
 
 }  // namespace lrep

@@ -94,16 +94,22 @@ int64_t lowrank_row_ld(int64_t r);
 // Lr (n x lowrank_row_ld(r), row-major, zero-padded) = L (n x r, ld ldl), r <= 256
 hipError_t lowrank_make_rows(hipStream_t st, int n, int r, const double* L, int64_t ldl, double* Lr);
 // C = delta o Y + 2 L (L^T Y) from the row-major copy, w <= 32 columns of Y
-// (ld even, 16-byte aligned); `work` holds 256 * 32 + nchunk * 8192 doubles
+// (ld even, 16-byte aligned); `work` holds 256 * 32 + nchunk * 8192 doubles.
+// With pq, also pq[t * 32 + j] = the sum over the 64-row tile t of Y[:, j] C[:, j].
 hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                                 const double* Y, int64_t ldy, double* C, int64_t ldc, double* work,
-                                size_t work_elems, const int* active_flag = nullptr, hipEvent_t* ev = nullptr);
+                                size_t work_elems, const int* active_flag = nullptr, hipEvent_t* ev = nullptr,
+                                double* pq = nullptr);
 
 // ---- vec.hip -------------------------------------------------------------
 // Y[:, j] = delta o X[:, j]
 hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta,
                       const double* X, int64_t ldx, double* Y, int64_t ldy,
                       const int* active_flag = nullptr);
+// the same for cols <= 32 with pq[t * 32 + j] = the sum over the 64-row tile
+// t of X[:, j] Y[:, j] (the CG's p . A p per tile)
+hipError_t diag_scale_pq(hipStream_t st, int n, int cols, const double* delta, const double* X, int64_t ldx,
+                         double* Y, int64_t ldy, double* pq, const int* active_flag = nullptr);
 
 // Step-4 residuals.  For Ritz columns j in [0, cols):
 //   eps[j] = sqrt(|KX_j - l_j Y_j|^2 + |MY_j - l_j X_j|^2) / ((1 + l_j) sqrt(|X_j|^2 + |Y_j|^2))
@@ -135,8 +141,10 @@ hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double*
 hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s);
 // alpha from the per-tile sums and cg_update in one launch: every block forms alpha of its
 // column from the tile sums in the same fixed order
-hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
-                           double tol);
+// pq holds cg_pq_elems(ntiles) doubles: the per-tile sums (ntiles x 32) and
+// room behind them where long tile lists are first folded 128 tiles at a time
+hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, double* pq, const CgState& s, double tol);
+size_t cg_pq_elems(int ntiles);
 // x += alpha p, r -= alpha q, rr_new, beta, active update
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
 // p = r + beta p for active columns

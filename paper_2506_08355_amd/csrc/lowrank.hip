@@ -179,6 +179,7 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
                                                       const double* __restrict__ delta,
                                                       const double* __restrict__ Y, int64_t ldy,
                                                       double* __restrict__ C, int64_t ldc,
+                                                      double* __restrict__ pq,
                                                       const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
     const int lane = threadIdx.x, c = lane % 16, g = lane / 16;
@@ -228,7 +229,14 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
         if (s + 1 < nunits) compute(a1, b1);
         __builtin_amdgcn_sched_barrier(0);
     }
-    // item r of (f, u): column 16 u + 4 r + g, row row0 + 16 f + c
+    // item r of (f, u): column 16 u + 4 r + g, row row0 + 16 f + c; with pq,
+    // also the tile's sums Y[:, col] . C[:, col] (the CG's p . A p), summed
+    // over f in order and then over the 16 lanes of the column
+    double yc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yc[u][r] = 0.0;
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -236,9 +244,26 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = row0 + 16 * f + c, col = 16 * u + 4 * r + g;
-                if (row < n && col < w)
-                    C[(int64_t)col * ldc + row] = fma(delta[row], Y[(int64_t)col * ldy + row], acc[f][u][r]);
+                if (row < n && col < w) {
+                    const double yv = Y[(int64_t)col * ldy + row];
+                    const double o = fma(delta[row], yv, acc[f][u][r]);
+                    C[(int64_t)col * ldc + row] = o;
+                    yc[u][r] = fma(yv, o, yc[u][r]);
+                }
             }
+    if (pq) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = yc[u][r];
+                v += __shfl_xor(v, 1, WAVE);
+                v += __shfl_xor(v, 2, WAVE);
+                v += __shfl_xor(v, 4, WAVE);
+                v += __shfl_xor(v, 8, WAVE);
+                if (c == 0) pq[(int64_t)blockIdx.x * 32 + 16 * u + 4 * r + g] = v;
+            }
+    }
 }
 
 }  // namespace
@@ -254,7 +279,7 @@ hipError_t lowrank_make_rows(hipStream_t st, int n, int r, const double* L, int6
 
 hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                                 const double* Y, int64_t ldy, double* C, int64_t ldc, double* work,
-                                size_t work_elems, const int* active_flag, hipEvent_t* ev) {
+                                size_t work_elems, const int* active_flag, hipEvent_t* ev, double* pq) {
     const int ldr = (int)lowrank_row_ld(r);
     if (w < 1 || w > 32 || r < 1 || r > 256 || n < 1 || (ldy & 1) || (reinterpret_cast<uintptr_t>(Y) & 15) ||
         (reinterpret_cast<uintptr_t>(Lr) & 31))
@@ -272,7 +297,7 @@ hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const doubl
                        active_flag);
     hipLaunchKernelGGL(lr_reduce_kernel, dim3(128), dim3(256), 0, st, ldr, nchunk, part, 2.0, Pt, active_flag);
     hipLaunchKernelGGL(lr_apply_kernel, dim3((n + RW - 1) / RW), dim3(64), 0, st, n, ldr, w, Lr, Pt, delta, Y, ldy,
-                       C, ldc, active_flag);
+                       C, ldc, pq, active_flag);
     if (ev) (void)hipEventRecord(ev[1], st);
     return hipGetLastError();
 }

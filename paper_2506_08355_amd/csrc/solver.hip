@@ -237,7 +237,7 @@ struct Solver {
                oG = carve(4 * D2), oC = carve((size_t)kproj * std::max(kMaxD, cw)),
                oT = carve((size_t)std::max<int64_t>(rank, 1) * kMaxD), opart = carve((size_t)256 * kMaxD * 4),
                orr = carve(kMaxD), obb = carve(kMaxD), oal = carve(kMaxD), obe = carve(kMaxD), oom = carve(8),
-               opq = carve(stream_tiles((int)n) * 32);
+               opq = carve(cg_pq_elems((int)stream_tiles((int)n)));
         CR(dsmall.alloc(c, nd * sizeof(double)));
         double* base = dsmall.p;
         Kh = base + oKh; Mh = base + oMh; S = base + oS; Xh = base + oXh; Yh = base + oYh;
@@ -285,8 +285,9 @@ struct Solver {
         return s;
     }
 
-    int apply(int which, const double* X, int cols, double* Y, const int* flag = nullptr, hipEvent_t* ev = nullptr) {
-        return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev);
+    int apply(int which, const double* X, int cols, double* Y, const int* flag = nullptr, hipEvent_t* ev = nullptr,
+              double* pq = nullptr) {
+        return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev, pq);
     }
 
     // the dense operator for the fused CG path (nullptr: use the generic apply)
@@ -304,6 +305,8 @@ struct Solver {
         CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
         const double* Ad = cg_stream_operator(which, nw);
         const int ntiles = (int)stream_tiles((int)n);
+        // low-rank operators: the apply also returns p.q per 64-row tile
+        const bool lr_pq = !Ad && op_apply_has_pq(op, which, cgP.p, n, nw);
         // mixed precision: the product on the 16-bit operator copy
         const uint16_t* A16 = nullptr;
         if (Ad && o.precision != 0 && op->prec16 == o.precision) {
@@ -332,6 +335,10 @@ struct Solver {
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
                                   cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
                 CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
+            } else if (lr_pq) {
+                CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev, cg_pq));
+                CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
+                CK(cg_direction(st, (int)n, nw, s));
             } else {
                 CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
                 CK(lrep::cg_alpha(st, (int)n, nw, s));
@@ -739,11 +746,30 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
 
 }  // namespace
 
+namespace {
+bool lowrank_rows_ok(const Op* op, const double* X, int64_t ldx) {
+    return op->Lr && (ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0;
+}
+}  // namespace
+
+bool op_apply_has_pq(const Op* op, int which, const double* X, int64_t ldx, int cols) {
+    if (op->kind != 1 || cols > 32) return false;
+    const bool useK = (which == 0) != op->null_on_M();
+    return useK || lowrank_rows_ok(op, X, ldx);
+}
+
 int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy,
-             double* work, size_t work_elems, double* small, const int* active_flag, hipEvent_t* ev) {
+             double* work, size_t work_elems, double* small, const int* active_flag, hipEvent_t* ev, double* pq) {
     if (cols <= 0) return LREP_OK;
     const bool useK = (which == 0) != op->null_on_M();
     hipError_t e = hipSuccess;
+    if (pq) {
+        if (!op_apply_has_pq(op, which, X, ldx, cols)) return LREP_EINVAL;
+        e = useK ? diag_scale_pq(st, (int)op->n, cols, op->delta, X, ldx, Y, ldy, pq, active_flag)
+                 : lowrank_apply_M_rows(st, (int)op->n, (int)op->rank, cols, op->delta, op->Lr, X, ldx, Y, ldy, work,
+                                        work_elems, active_flag, ev, pq);
+        return e == hipSuccess ? LREP_OK : LREP_EDEVICE;
+    }
     if (op->kind == 2) {
         const int rc = op->apply_fn(op->apply_user, useK ? 0 : 1, cols, X, ldx, Y, ldy, st);
         if (rc != 0) {
@@ -765,7 +791,7 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
         }
     } else if (useK) {
         e = diag_scale(st, (int)op->n, cols, op->delta, X, ldx, Y, ldy, active_flag);
-    } else if (op->Lr && (ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) {
+    } else if (lowrank_rows_ok(op, X, ldx)) {
         // streaming low-rank apply on the row-major copy, 32 columns at a time
         for (int c0 = 0; c0 < cols && e == hipSuccess; c0 += 32) {
             const int w = std::min(32, cols - c0);

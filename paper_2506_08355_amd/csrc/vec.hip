@@ -27,6 +27,32 @@ __global__ __launch_bounds__(NT) void diag_scale_kernel(int n, int cols, const d
         Y[(int64_t)j * ldy + i] = delta[i] * X[(int64_t)j * ldx + i];
 }
 
+// block (tile of 64 rows) x 256 threads: thread = (row, column group of 8);
+// per column the tile's sum of x y, rows in wave-sum order
+__global__ __launch_bounds__(NT) void diag_scale_pq_kernel(int n, int cols, const double* __restrict__ delta,
+                                                           const double* __restrict__ X, int64_t ldx,
+                                                           double* __restrict__ Y, int64_t ldy,
+                                                           double* __restrict__ pq,
+                                                           const int* __restrict__ active_flag) {
+    if (active_flag && *active_flag == 0) return;
+    const int i = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const int row = blockIdx.x * 64 + i;
+    const double dv = row < n ? delta[row] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int col = grp * 8 + u;
+        double s = 0.0;
+        if (col < cols && row < n) {
+            const double x = X[(int64_t)col * ldx + row];
+            const double y = dv * x;
+            Y[(int64_t)col * ldy + row] = y;
+            s = x * y;
+        }
+        s = wave_sum(s);
+        if (i == 0 && col < cols) pq[(int64_t)blockIdx.x * 32 + col] = s;
+    }
+}
+
 // ---------------------------------------------------------------- residuals
 __global__ __launch_bounds__(NT) void residual_kernel(int n, int cols, int nchunks, const double* __restrict__ X,
                                                       const double* __restrict__ Y, const double* __restrict__ KX,
@@ -211,6 +237,30 @@ __device__ void cg_fin_wave(int w, int nchunks, const CgState& s, double tol) {
 __global__ __launch_bounds__(64) void cg_update_fin_kernel(int w, int nchunks, CgState s, double tol) {
     if (*s.any_active == 0) return;
     cg_fin_wave(w, nchunks, s, tol);
+}
+
+constexpr int kFold = 128;   // tiles per block of cg_fold_pq_kernel
+
+// folded[b * 32 + j] = sum of pq[k * 32 + j] over tiles k in [128 b, 128 b + 128):
+// thread (j = t % 32, s = t / 32) sums k = 128 b + s, + 8, ..., the eight
+// partial sums are then added in order of s
+__global__ __launch_bounds__(NT) void cg_fold_pq_kernel(int ntiles, const double* __restrict__ pq,
+                                                        double* __restrict__ folded, const int* __restrict__ any) {
+    static_assert(NT == 256, "32 columns x 8 tile phases");
+    __shared__ double red[8][32];
+    if (*any == 0) return;
+    const int j = threadIdx.x % 32, sub = threadIdx.x / 32;
+    const int k0 = blockIdx.x * kFold;
+    double acc = 0.0;
+    for (int k = k0 + sub; k < min(ntiles, k0 + kFold); k += 8) acc += pq[(int64_t)k * 32 + j];
+    red[sub][j] = acc;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += red[q][j];
+        folded[(int64_t)blockIdx.x * 32 + j] = t;
+    }
 }
 
 __global__ __launch_bounds__(NT) void cg_update_tiles_kernel(int n, int w, int nchunks, int ntiles,
@@ -429,6 +479,15 @@ hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta, cons
     return hipGetLastError();
 }
 
+hipError_t diag_scale_pq(hipStream_t st, int n, int cols, const double* delta, const double* X, int64_t ldx,
+                         double* Y, int64_t ldy, double* pq, const int* active_flag) {
+    if (cols <= 0) return hipSuccess;
+    if (cols > 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_scale_pq_kernel, dim3((n + 63) / 64), dim3(NT), 0, st, n, cols, delta, X, ldx, Y, ldy, pq,
+                       active_flag);
+    return hipGetLastError();
+}
+
 hipError_t residual_eps(hipStream_t st, int n, int cols, const double* X, const double* Y, const double* KX,
                         const double* MY, int64_t ld, const double* lam, double* eps, double* part,
                         size_t part_elems, unsigned* ticket) {
@@ -509,8 +568,17 @@ hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
     if (!fin) hipLaunchKernelGGL(cg_alpha_fin_kernel, dim3(1), dim3(64), 0, st, w, nch, s);
     return hipGetLastError();
 }
-hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, const double* pq, const CgState& s,
-                           double tol) {
+size_t cg_pq_elems(int ntiles) { return (size_t)(ntiles + (ntiles + kFold - 1) / kFold) * 32; }
+
+hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, double* pq, const CgState& s, double tol) {
+    if (ntiles > 2 * kFold) {
+        // every update block would otherwise walk the whole strided tile list
+        const int nb = (ntiles + kFold - 1) / kFold;
+        double* folded = pq + (size_t)ntiles * 32;
+        hipLaunchKernelGGL(cg_fold_pq_kernel, dim3(nb), dim3(NT), 0, st, ntiles, pq, folded, s.any_active);
+        pq = folded;
+        ntiles = nb;
+    }
     const int nch = cg_chunks(n, w, s);
     const int fin = fuse_fin(nch, w);
     hipLaunchKernelGGL(cg_update_tiles_kernel, dim3(nch, w), dim3(NT), 0, st, n, w, nch, ntiles, pq, s, tol, fin);
