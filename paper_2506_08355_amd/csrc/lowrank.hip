@@ -63,14 +63,16 @@ __global__ __launch_bounds__(256) void lr_lty_kernel(int n, int ldr, int w, cons
         const bool yok0 = yc0 < w, yok1 = yc1 < w;
         const double* yp0 = Y + (int64_t)(yok0 ? yc0 : 0) * ldy + i_begin + 4 * g;
         const double* yp1 = Y + (int64_t)(yok1 ? yc1 : 0) * ldy + i_begin + 4 * g;
-        auto compute = [&](const double (&a)[4][4], const double2 (&b)[2][2]) {
+        // use = false (wavefront-uniform) multiplies the unit by zero
+        auto compute = [&](const double (&a)[4][4], const double2 (&b)[2][2], bool use) {
+            const bool u0 = yok0 && use, u1 = yok1 && use;
             double bb[2][4];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                bb[0][2 * h] = yok0 ? b[0][h].x : 0.0;
-                bb[0][2 * h + 1] = yok0 ? b[0][h].y : 0.0;
-                bb[1][2 * h] = yok1 ? b[1][h].x : 0.0;
-                bb[1][2 * h + 1] = yok1 ? b[1][h].y : 0.0;
+                bb[0][2 * h] = u0 ? b[0][h].x : 0.0;
+                bb[0][2 * h + 1] = u0 ? b[0][h].y : 0.0;
+                bb[1][2 * h] = u1 ? b[1][h].x : 0.0;
+                bb[1][2 * h + 1] = u1 ? b[1][h].y : 0.0;
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -96,15 +98,18 @@ __global__ __launch_bounds__(256) void lr_lty_kernel(int n, int ldr, int w, cons
                     b[1][h] = *reinterpret_cast<const double2*>(yp1 + o + 2 * h);
                 }
             };
+            // both halves are computed unconditionally (a surplus odd unit
+            // counts zero): with a conditional second half the compiler sinks
+            // its loads behind the first half's products and nothing overlaps
             load(a0, b0, 0);
             for (int s = 0; s < nfull; s += 2) {
                 load(a1, b1, s + 1);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(a0, b0);
+                compute(a0, b0, true);
                 __builtin_amdgcn_sched_barrier(0);
                 load(a0, b0, s + 2);
                 __builtin_amdgcn_sched_barrier(0);
-                if (s + 1 < nfull) compute(a1, b1);
+                compute(a1, b1, s + 1 < nfull);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(256) void lr_lty_kernel(int n, int ldr, int w, cons
                 b[1][h] = double2{(yok1 && ia < i_end) ? Y[(int64_t)yc1 * ldy + ia] : 0.0,
                                   (yok1 && ib < i_end) ? Y[(int64_t)yc1 * ldy + ib] : 0.0};
             }
-            compute(a, b);
+            compute(a, b, true);
         }
     }
     double* out = part + ((int64_t)blockIdx.x * 256 + threadIdx.x) * 32;
@@ -144,27 +149,30 @@ __global__ __launch_bounds__(256) void lr_lty_kernel(int n, int ldr, int w, cons
 
 // T (k-major, rows 0 .. ldr - 1, 32 columns) = alpha * sum over the chunks of
 // the partial tiles, in a fixed order.  Block b handles entries
-// [64 b, 64 b + 64) of the per-workgroup tile (lane order of lr_lty_kernel);
-// its four wavefronts sum the chunks k = wv, wv + 4, ... and wavefront 0 adds
-// the four partial sums in order.
-__global__ __launch_bounds__(256) void lr_reduce_kernel(int ldr, int nchunk, const double* __restrict__ part,
-                                                        double alpha, double* __restrict__ Pt,
-                                                        const int* __restrict__ flag) {
+// [32 b, 32 b + 32) of the per-workgroup tile (lane order of lr_lty_kernel);
+// thread (entry t % 32, phase q = t / 32) sums the chunks q, q + 16, ... in
+// two interleaved partial sums, and the 16 phase sums are added in order.
+constexpr int RED_PH = 16;
+__global__ __launch_bounds__(32 * RED_PH) void lr_reduce_kernel(int ldr, int nchunk, const double* __restrict__ part,
+                                                               double alpha, double* __restrict__ Pt,
+                                                               const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int e = blockIdx.x * 64 + lane;   // < 8192
+    __shared__ double red[RED_PH][32];
+    const int x = threadIdx.x % 32, q = threadIdx.x / 32;
+    const int e = blockIdx.x * 32 + x;   // < 8192
     double s0 = 0.0, s1 = 0.0;
-    int k = wv;
-    for (; k + 4 < nchunk; k += 8) {
+    int k = q;
+    for (; k + RED_PH < nchunk; k += 2 * RED_PH) {
         s0 += part[(int64_t)k * 8192 + e];
-        s1 += part[(int64_t)(k + 4) * 8192 + e];
+        s1 += part[(int64_t)(k + RED_PH) * 8192 + e];
     }
     if (k < nchunk) s0 += part[(int64_t)k * 8192 + e];
-    red[wv][lane] = s0 + s1;
+    red[q][x] = s0 + s1;
     __syncthreads();
-    if (wv != 0) return;
-    const double s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (q != 0) return;
+    double s = red[0][x];
+#pragma unroll
+    for (int p = 1; p < RED_PH; ++p) s += red[p][x];
     const int tl = e / 32, v = e % 32;               // thread of the partial tile, item
     const int pw = tl / WAVE, pl = tl % WAVE;
     const int t = v / 8, u = (v / 4) % 2, it = v % 4;
@@ -218,6 +226,8 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
                     acc[f][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u][e], av, acc[f][u], 0, 0, 0);
             }
     };
+    // nunits is a multiple of 4, so both halves always run; they carry no
+    // condition, which keeps the next half's loads ahead of the products
     load(a0, b0, 0);
     for (int s = 0; s < nunits; s += 2) {
         load(a1, b1, s + 1);
@@ -226,7 +236,7 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
         __builtin_amdgcn_sched_barrier(0);
         load(a0, b0, s + 2);
         __builtin_amdgcn_sched_barrier(0);
-        if (s + 1 < nunits) compute(a1, b1);
+        compute(a1, b1);
         __builtin_amdgcn_sched_barrier(0);
     }
     // item r of (f, u): column 16 u + 4 r + g, row row0 + 16 f + c; with pq,
@@ -295,7 +305,8 @@ hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const doubl
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(lr_lty_kernel, dim3(nchunk), dim3(256), 0, st, n, ldr, w, Lr, Y, ldy, chunk, part,
                        active_flag);
-    hipLaunchKernelGGL(lr_reduce_kernel, dim3(128), dim3(256), 0, st, ldr, nchunk, part, 2.0, Pt, active_flag);
+    hipLaunchKernelGGL(lr_reduce_kernel, dim3(8192 / 32), dim3(32 * RED_PH), 0, st, ldr, nchunk, part, 2.0, Pt,
+                       active_flag);
     hipLaunchKernelGGL(lr_apply_kernel, dim3((n + RW - 1) / RW), dim3(64), 0, st, n, ldr, w, Lr, Pt, delta, Y, ldy,
                        C, ldc, pq, active_flag);
     if (ev) (void)hipEventRecord(ev[1], st);
