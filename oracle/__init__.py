@@ -13,6 +13,8 @@ Modules
   bosp        the BOSP iteration with batching/moving (Algorithm "BOSP
               algorithm", Sections 3.2-3.3), dense and Casida operators
   exact       exact spectra of the synthetic workloads (pins)
+  generalized the generalized LREP with an SPD metric B (eigenvalues by
+              reduction to standard form, residuals, B-biorthogonality)
 
 Every function is pinned by a CPU test (``pytest -m "not gpu"``) against
 values the paper prints, closed forms, or exact identities.
@@ -22,11 +24,11 @@ from .small_lrep import small_lrep, small_lrep_bruteforce, NotSPDError
 from .bosp import (DenseOperator, CasidaOperator, bosp_solve, cg_columns,
                    residual_eps, sign_normalise, nullspace_basis, BospResult,
                    NotConvergedError)
-from . import exact
+from . import exact, generalized
 
 __all__ = [
     "mgs_biorth", "cgs_biorth", "small_lrep", "small_lrep_bruteforce",
     "NotSPDError", "DenseOperator", "CasidaOperator", "bosp_solve",
     "cg_columns", "residual_eps", "sign_normalise", "nullspace_basis",
-    "BospResult", "NotConvergedError", "exact",
+    "BospResult", "NotConvergedError", "exact", "generalized",
 ]
