@@ -27,6 +27,11 @@ Workloads (sizes and distributions follow the benchmark configurations):
            experiment (Section 3.1, table of biorthogonality loss).
 * init:    the random starting block (U, V) of Step 1 of the BOSP algorithm,
            standard normal, U drawn before V.
+* metric:  the diagonal b of an SPD metric B = diag(b) for the generalized
+           LREP K x = lambda B y, M y = lambda B x: log-uniform on [lo, hi]
+           (default [0.25, 4]), a stand-in for a lumped finite-element mass
+           matrix (the paper's Example 4.5 uses a P3 mass matrix, not
+           available here).  One draw of n uniforms.
 """
 from __future__ import annotations
 
@@ -44,6 +49,7 @@ __all__ = [
     "DenseFactors",
     "CasidaFactors",
     "dense_operator_device",
+    "metric_diag",
 ]
 
 
@@ -199,3 +205,9 @@ def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
     if return_factors:
         return out[0], out[1], k, m, qs[0], qs[1]
     return out[0], out[1], k, m
+
+
+def metric_diag(n: int, seed: int, lo: float = 0.25, hi: float = 4.0) -> np.ndarray:
+    """Diagonal of the SPD metric B: exp(U[log lo, log hi]) per entry."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n))

@@ -209,6 +209,32 @@ int lrep_create_callback(lrep_ctx_t ctx, int64_t n, lrep_apply_fn apply, void* u
  * Errors: LREP_EINVAL, LREP_ENOTSPD (X0~^T Y0~ not SPD), LREP_ENOMEM. */
 int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, int32_t on_device);
 
+/* Generalized LREP with a diagonal SPD metric (the remark on the generalized
+ * LREP in Section 3.2; Example 4.5 has this form):
+ *     K x = lambda B y,   M y = lambda B x,   B = diag(b), b_i > 0,
+ * solved in the B inner product <u, v>_B = u^T B v.  b (n values, host, or
+ * device with LREP_DEVICE_PTR in flags; n must equal the operator's) is read
+ * once.  With S = B^-1/2 the
+ * pencil is the standard LREP of S K S and S M S in x^ = B^1/2 x, y^ =
+ * B^1/2 y, and Euclidean MGS-Biorth on (x^, y^) is MGS-Biorth in the B inner
+ * product on (x, y); the library scales its copy of the operator once
+ * (dense: K and M; low rank: delta and L) and keeps S.  Afterwards:
+ *   - lrep_set_nullspace takes X0 spanning N(K) (or N(M)) in the original
+ *     coordinates;
+ *   - a start block in opts.init is taken in the original coordinates;
+ *   - lrep_solve returns X, Y in the original coordinates with
+ *     Y^T B X = I, and stats.max_eps / the convergence test use the
+ *     residual of the scaled pencil, ||S (K x - lambda B y)|| and
+ *     ||S (M y - lambda B x)||, over (1 + lambda) ||(x^, y^)||.
+ * Call it at most once per operator, before lrep_set_nullspace, and not
+ * while a solve of the operator runs.  Operators from lrep_create_callback
+ * and operators that borrow the caller's arrays (LREP_BORROW) are refused:
+ * their data is not the library's to scale (a callback can apply S K S
+ * itself).  Nothing is changed when an error is returned.
+ * Errors: LREP_EINVAL (also for an entry of b that is not positive and
+ * finite), LREP_ENOMEM, LREP_EDEVICE. */
+int lrep_set_metric(lrep_op_t op, int64_t n, const double* b, uint32_t flags);
+
 /* Free an operator's device memory (borrowed arrays are not freed). */
 int lrep_destroy_op(lrep_op_t op);
 

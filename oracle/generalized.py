@@ -1,5 +1,5 @@
 """Generalized LREP with an SPD metric B (the remark on the generalized LREP
-in Section 3; the finite-element problem of Example 4.5), plain FP64.
+in Section 3.2; the finite-element problem of Example 4.5), plain FP64.
 
 TEST INFRASTRUCTURE ONLY -- part of the CPU oracle.
 
@@ -72,3 +72,17 @@ def generalized_residual(K, M, B, X, Y, lam, normH=None, normB=None):
 def b_biorth_error(B, X, Y) -> float:
     """max |Y^T B X - I|."""
     return float(np.abs(Y.T @ (B @ X) - np.eye(X.shape[1])).max())
+
+
+def dense_metric_spectrum_smallest(q1, k, q2, m, b, count, zeros: int = 0):
+    """The ``count`` smallest positive eigenvalues for the dense workload
+    K = Q1 diag(k) Q1^T, M = Q2 diag(m) Q2^T with the diagonal metric
+    B = diag(b), for large n.  With S = B^-1/2 the scaled pencil has factors
+    F1 = S Q1 diag(sqrt k), F2 = S Q2 diag(sqrt m), so the eigenvalues are the
+    singular values of F = diag(sqrt k) Q1^T B^-1 Q2 diag(sqrt m); their
+    squares are taken from F^T F with a symmetric eigensolver restricted to
+    the index range (``zeros`` exact zeros of m are skipped)."""
+    import scipy.linalg as sla
+    F = (np.sqrt(k)[:, None] * (q1.T @ (q2 / b[:, None]))) * np.sqrt(m)[None, :]
+    w = sla.eigh(F.T @ F, eigvals_only=True, subset_by_index=[zeros, zeros + count - 1], driver="evr")
+    return np.sqrt(np.maximum(w, 0.0))

@@ -121,6 +121,7 @@ _SIGS = {
     "lrep_create_lowrank": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_create_callback": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_set_nullspace": (ctypes.c_int, [_P, _I64, _P, _I64, _I32]),
+    "lrep_set_metric": (ctypes.c_int, [_P, _I64, _P, ctypes.c_uint32]),
     "lrep_destroy_op": (ctypes.c_int, [_P]),
     "lrep_solve": (ctypes.c_int, [_P, _I64, _I64, _I64, _D, ctypes.POINTER(lrep_solve_opts_t), _P, _P, _P, _I64,
                                   ctypes.POINTER(lrep_stats_t)]),
@@ -282,6 +283,15 @@ def lrep_set_nullspace(op, X0, ctx=None):
         return _check(lib().lrep_set_nullspace(op, 0, None, 1, 0), ctx, "lrep_set_nullspace")
     p, ld, dev = colmajor(X0)
     return _check(lib().lrep_set_nullspace(op, X0.shape[1], p, ld, int(dev)), ctx, "lrep_set_nullspace")
+
+
+def lrep_set_metric(op, b, ctx=None):
+    """Diagonal metric B = diag(b) of a generalized LREP (b: n positive
+    values, a NumPy array or a device tensor)."""
+    if b.ndim != 1:
+        raise ValueError("b must be a vector")
+    p, _, dev = colmajor(b)
+    return _check(lib().lrep_set_metric(op, b.shape[0], p, LREP_DEVICE_PTR if dev else 0), ctx, "lrep_set_metric")
 
 
 def lrep_destroy_op(op):

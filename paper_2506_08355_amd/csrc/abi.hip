@@ -298,6 +298,8 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
     if (rc != LREP_OK) return rc;
     hipError_t e = hipMemcpy2DAsync(tmp.p, op->n * sizeof(double), X0, ld * sizeof(double), op->n * sizeof(double), r,
                                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+    // with a metric, N(S K S) = S^-1 N(K)
+    if (e == hipSuccess && op->Sv) e = metric_scale_rows(c->stream, op->n, (int)r, tmp.p, op->n, op->Sv, true);
     if (e != hipSuccess) return LREP_EDEVICE;
     rc = prepare_nullspace(op, c->stream, r, tmp.p);
     if (rc != LREP_OK) {
@@ -306,6 +308,67 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
         op->Y0.release();
     }
     return rc;
+}
+
+int lrep_set_metric(lrep_op_t op, int64_t n_b, const double* b, uint32_t flags) {
+    if (!op || !b || n_b != op->n) return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    auto refuse = [&](const char* why) {
+        c->set_error(why);
+        return LREP_EINVAL;
+    };
+    if (op->kind == 2) return refuse("lrep_set_metric: a callback operator applies the scaled pencil itself");
+    if (op->Sv) return refuse("lrep_set_metric: the operator already has a metric");
+    if (op->r0 > 0) return refuse("lrep_set_metric: set the metric before the null space");
+    const bool owned = op->kind == 0 ? (op->K == op->Kbuf.p && op->M == op->Mbuf.p)
+                                     : (op->delta == op->dbuf.p && (op->rank == 0 || op->L == op->Lbuf.p));
+    if (!owned) return refuse("lrep_set_metric: the operator borrows the caller's arrays");
+    const int64_t n = op->n;
+    DevBuf sb, bb, flag;
+    int rc = sb.alloc(c, (size_t)n * sizeof(double));
+    if (rc == LREP_OK && !(flags & LREP_DEVICE_PTR)) rc = bb.alloc(c, (size_t)n * sizeof(double));
+    if (rc == LREP_OK) rc = flag.alloc(c, sizeof(double));
+    if (rc != LREP_OK) return rc;
+    const double* bd = b;
+    int* bad = reinterpret_cast<int*>(flag.p);
+    hipError_t e = hipSuccess;
+    if (!(flags & LREP_DEVICE_PTR)) {
+        e = hipMemcpyAsync(bb.p, b, (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        bd = bb.p;
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = metric_prepare(c->stream, n, bd, sb.p, bad);
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->set_error(hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    if (hbad) return refuse("lrep_set_metric: every entry of b must be positive and finite");
+    const double* sv = sb.p;
+    if (op->kind == 0) {
+        e = metric_scale_sym(c->stream, n, op->K, op->ld, sv);
+        if (e == hipSuccess) e = metric_scale_sym(c->stream, n, op->M, op->ld, sv);
+        // 16-bit copies, if any, were made from the unscaled operator
+        std::lock_guard<std::mutex> lk(op->mu16);
+        op->prec16 = 0;
+        op->K16buf.release();
+        op->M16buf.release();
+    } else {
+        e = metric_scale_diag(c->stream, n, op->delta, sv);
+        if (e == hipSuccess && op->rank > 0) e = metric_scale_rows(c->stream, n, (int)op->rank, op->L, op->ldl, sv, false);
+        if (e == hipSuccess && op->Lr) e = lowrank_make_rows(c->stream, (int)n, (int)op->rank, op->L, op->ldl, op->Lr);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->set_error(hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    op->Sbuf.take(sb);
+    op->Sv = op->Sbuf.p;
+    return LREP_OK;
 }
 
 int lrep_destroy_op(lrep_op_t op) {

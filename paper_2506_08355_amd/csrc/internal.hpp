@@ -31,6 +31,16 @@ struct DevBuf {
     ~DevBuf();
     int alloc(Ctx* c, size_t nbytes);   // LREP_OK / LREP_ENOMEM / LREP_EDEVICE
     void release();
+    // take over o's allocation (o is left empty)
+    void take(DevBuf& o) {
+        release();
+        ctx = o.ctx;
+        p = o.p;
+        bytes = o.bytes;
+        o.ctx = nullptr;
+        o.p = nullptr;
+        o.bytes = 0;
+    }
 };
 
 struct Op {
@@ -54,6 +64,10 @@ struct Op {
     // caller-supplied products
     lrep_apply_fn apply_fn = nullptr;
     void* apply_user = nullptr;
+    // diagonal metric B = diag(b) of a generalized LREP: Sv = b^-1/2 (device,
+    // n values); the operator data above is already the scaled S K S, S M S
+    DevBuf Sbuf;
+    double* Sv = nullptr;
     // generalized null space, biorthonormal X0^T Y0 = I (roles already exchanged)
     int64_t r0 = 0;
     DevBuf X0, Y0;

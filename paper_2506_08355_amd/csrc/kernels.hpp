@@ -102,6 +102,17 @@ hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const doubl
                                 double* pq = nullptr);
 
 // ---- vec.hip -------------------------------------------------------------
+// ---- diagonal metric (metric.hip)
+// s = b^-1/2 where every b_i is positive and finite; else *bad = 1
+hipError_t metric_prepare(hipStream_t st, int64_t n, const double* b, double* s, int* bad);
+// A (n x n, ld) <- diag(s) A diag(s)
+hipError_t metric_scale_sym(hipStream_t st, int64_t n, double* A, int64_t ld, const double* s);
+// d <- s o s o d
+hipError_t metric_scale_diag(hipStream_t st, int64_t n, double* d, const double* s);
+// X (n x cols, ld) <- diag(s) X, or diag(s)^-1 X with inverse
+hipError_t metric_scale_rows(hipStream_t st, int64_t n, int cols, double* X, int64_t ldx, const double* s,
+                             bool inverse);
+
 // Y[:, j] = delta o X[:, j]
 hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta,
                       const double* X, int64_t ldx, double* Y, int64_t ldy,

@@ -446,6 +446,8 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         else
             CK(hipMemcpy2DAsync(U0, n * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
                                 d0, hipMemcpyHostToDevice, st));
+        // with a metric the start block is given in the original coordinates
+        if (op->Sv) CK(metric_scale_rows(st, n, d0, U0, n, op->Sv, true));
     } else {
         CK(philox_normal(st, (int)n, d0, o.seed, U0, n));
     }
@@ -730,6 +732,10 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     if (c > 0) {
         double* OX = op->null_on_M() ? Yc.p : Xc.p;
         double* OY = op->null_on_M() ? Xc.p : Yc.p;
+        if (op->Sv) {   // back to the original coordinates: x = S x^, y = S y^
+            CK(metric_scale_rows(st, n, c, OX, n, op->Sv, false));
+            CK(metric_scale_rows(st, n, c, OY, n, op->Sv, false));
+        }
         CK(sign_normalise(st, (int)n, c, OX, OY, n));
         const hipMemcpyKind kind = o.result_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         CK(hipMemcpy2DAsync(X_out, ldxy * sizeof(double), OX, n * sizeof(double), n * sizeof(double), c, kind, st));

@@ -108,3 +108,30 @@ def test_config3_casida_full_size(ctx):
         lk = lam[kk - 1]
         assert exact.casida_count_below(dl, Lh, lk * (1 - 1e-10)) <= kk - 1, kk
         assert exact.casida_count_below(dl, Lh, lk * (1 + 1e-10)) >= kk, kk
+
+
+def test_config2_full_size_metric(ctx):
+    """The dense n = 8192 workload as a generalized LREP with a diagonal
+    metric B (K x = lambda B y, M y = lambda B x): eigenvalues against the
+    oracle's factored form, the pencil's backward error <= 1e-8 and
+    max |Y^T B X - I| <= 1e-12."""
+    from oracle import generalized as G
+    n, nev, block, window, tol = 8192, 64, 64, 32, 1e-10
+    print(f"[fullsize] dense n={n} metric", flush=True)
+    Kd, Md, k, m, Q1, Q2 = gen.dense_operator_device(n, 1002, "cuda:0", return_factors=True)
+    b = gen.metric_diag(n, 1105)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_dense(ctx, Kd.T, Md.T)
+    L.lrep_set_metric(op, b, ctx)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    print(f"[fullsize] iterations {st.iterations}", flush=True)
+    K, M = Kd.cpu().numpy(), Md.cpu().numpy()
+    del Kd, Md
+    ref = G.dense_metric_spectrum_smallest(Q1.cpu().numpy(), k, Q2.cpu().numpy(), m, b, nev)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+    B = np.diag(b)
+    res = G.generalized_residual(K, M, B, X, Y, lam, normH=float(max(k.max(), m.max())), normB=float(b.max()))
+    assert res.max() <= 1e-8, res.max()
+    assert G.b_biorth_error(B, X, Y) <= 1e-12

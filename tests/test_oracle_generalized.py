@@ -95,3 +95,17 @@ def test_residual_and_biorth_of_exact_pairs():
     assert G.b_biorth_error(B, X, Y) < 1e-12
     assert G.generalized_residual(K, M, np.eye(n), X, Y, lam).max() > 1e-3
     assert G.generalized_residual(K, M, B, X, Y, lam * (1 + 1e-6)).max() > 1e-8
+
+
+@pytest.mark.parametrize("n_zero_m", [0, 3])
+def test_dense_metric_factored_form_against_reduction(n_zero_m):
+    # the large-n factored form of the dense workload with a diagonal metric
+    # against the Cholesky reduction of the assembled matrices
+    import gen
+    n, count = 60, 12
+    f = gen.dense_factors(n, 21, n_zero_m=n_zero_m)
+    b = gen.metric_diag(n, 22)
+    K, M = (f.q1 * f.k) @ f.q1.T, (f.q2 * f.m) @ f.q2.T
+    ref = G.generalized_spectrum(K, M, np.diag(b), count, zeros=n_zero_m)
+    got = G.dense_metric_spectrum_smallest(f.q1, f.k, f.q2, f.m, b, count, zeros=n_zero_m)
+    np.testing.assert_allclose(got, ref, rtol=1e-11)
