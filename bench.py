@@ -53,6 +53,9 @@ WORKLOADS = {
     "dense8192fp16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                           precision=2),
     "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8),
+    # generalized LREP K x = lambda B y, M y = lambda B x with a diagonal metric B (growth direction f4)
+    "dense8192metric": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                            metric_seed=1105),
 }
 
 
@@ -221,6 +224,8 @@ def describe(w):
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
         z += {0: "", 1: "; CG applies in BF16 (f32 accumulate)", 2: "; CG applies in FP16 (f32 accumulate)"}[
             w.get("precision", 0)]
+        if w.get("metric_seed"):
+            z += "; generalized LREP K x = lambda B y, M y = lambda B x, B = diag(b), b log-uniform on [0.25, 4]"
         return (f"dense FP64 n={w['n']}: K=Q1 diag(k) Q1^T, M=Q2 diag(m) Q2^T, Haar Q1/Q2, k,m~U[0.5,10]{z}; "
                 f"nev={w['nev']}, block={w['block']}, window={w['window']}, tol={w['tol']:g}")
     return (f"Casida low-rank FP64 n={w['n']}: K=diag(delta), M=diag(delta)+2LL^T, delta~U[0.1,20] sorted, "
@@ -307,6 +312,9 @@ def main():
     ctx = L.lrep_init(0)
     if w["kind"] == "dense":
         op = L.lrep_create_dense(ctx, Kd.T, Md.T, L.LREP_NULL_ON_M if w["zeros"] else 0)
+        if w.get("metric_seed"):
+            bmetric = gen.metric_diag(n, w["metric_seed"])
+            L.lrep_set_metric(op, bmetric, ctx)
         if w["zeros"]:
             L.lrep_set_nullspace(op, null, ctx)     # the 8 columns of Q2 with m = 0
     else:
@@ -362,12 +370,22 @@ def main():
                     v = delta_d * v + 2.0 * (L_d @ (L_d.T @ v))
                     v = v / torch.linalg.norm(v)
                 normH = float(torch.dot(v, delta_d * v + 2.0 * (L_d @ (L_d.T @ v))))
-        R1 = KX - Y * lam[None, :]
-        R2 = MY - X * lam[None, :]
-        res = torch.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (
-            normH * torch.sqrt((X ** 2).sum(0) + (Y ** 2).sum(0)))
+        if w.get("metric_seed"):
+            # generalized pencil: residuals K x - lambda B y, M y - lambda B x over
+            # (||H|| + lambda ||B||) ||(x, y)||, and Y^T B X = I
+            bd = torch.from_numpy(bmetric).to(dev)[:, None]
+            R1 = KX - (bd * Y) * lam[None, :]
+            R2 = MY - (bd * X) * lam[None, :]
+            res = torch.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (
+                (normH + lam * float(bmetric.max())) * torch.sqrt((X ** 2).sum(0) + (Y ** 2).sum(0)))
+            biorth = float((Y.T @ (bd * X) - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max())
+        else:
+            R1 = KX - Y * lam[None, :]
+            R2 = MY - X * lam[None, :]
+            res = torch.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (
+                normH * torch.sqrt((X ** 2).sum(0) + (Y ** 2).sum(0)))
+            biorth = float((X.T @ Y - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max())
         max_res = float(res.max())
-        biorth = float((X.T @ Y - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max())
 
     achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else None
     roofline = None
@@ -401,7 +419,12 @@ def main():
         except Exception:
             cores = os.cpu_count()
         print(f"[bench] CPU oracle sample: {args.cpu_iters} iterations ...", file=sys.stderr, flush=True)
-        if w["kind"] == "dense":
+        if w["kind"] == "dense" and w.get("metric_seed"):
+            # the scaled pencil S K S, S M S (S = B^-1/2) that the library solves
+            sv = 1.0 / np.sqrt(bmetric)
+            cop = oracle.DenseOperator(sv[:, None] * Kd.cpu().numpy() * sv[None, :],
+                                       sv[:, None] * Md.cpu().numpy() * sv[None, :])
+        elif w["kind"] == "dense":
             cop = oracle.DenseOperator(Kd.cpu().numpy(), Md.cpu().numpy())
         else:
             cop = oracle.CasidaOperator(f.delta, f.L)
