@@ -15,6 +15,8 @@ Modules
   exact       exact spectra of the synthetic workloads (pins)
   generalized the generalized LREP with an SPD metric B (eigenvalues by
               reduction to standard form, residuals, B-biorthogonality)
+  nullspace   basis of N(K) from a symmetric eigendecomposition, subspace
+              distance (principal angles)
 
 Every function is pinned by a CPU test (``pytest -m "not gpu"``) against
 values the paper prints, closed forms, or exact identities.
@@ -24,11 +26,11 @@ from .small_lrep import small_lrep, small_lrep_bruteforce, NotSPDError
 from .bosp import (DenseOperator, CasidaOperator, bosp_solve, cg_columns,
                    residual_eps, sign_normalise, nullspace_basis, BospResult,
                    NotConvergedError)
-from . import exact, generalized
+from . import exact, generalized, nullspace
 
 __all__ = [
     "mgs_biorth", "cgs_biorth", "small_lrep", "small_lrep_bruteforce",
     "NotSPDError", "DenseOperator", "CasidaOperator", "bosp_solve",
     "cg_columns", "residual_eps", "sign_normalise", "nullspace_basis",
-    "BospResult", "NotConvergedError", "exact", "generalized",
+    "BospResult", "NotConvergedError", "exact", "generalized", "nullspace",
 ]
