@@ -209,6 +209,24 @@ int lrep_create_callback(lrep_ctx_t ctx, int64_t n, lrep_apply_fn apply, void* u
  * Errors: LREP_EINVAL, LREP_ENOTSPD (X0~^T Y0~ not SPD), LREP_ENOMEM. */
 int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, int32_t on_device);
 
+/* Compute the null space instead of declaring it (the remark on computing the
+ * generalized null space, Section 2.2: the zero eigenvectors of the
+ * semidefinite operator A = K, or M with LREP_NULL_ON_M).  rmax (1..64,
+ * below n) random vectors from `seed` are projected onto N(A) by CG on
+ * A x = A x0 from a zero start (x0 - x is x0's component in N(A)); the
+ * projections are orthonormalised by block MGS, which drops dependent ones,
+ * and projections at rounding level are discarded.  The basis found is then
+ * declared as with lrep_set_nullspace (r = 0 clears any earlier one).
+ * *r_out (required) receives its dimension r; r == rmax means N(A) may be
+ * larger: call again with a larger rmax.  *res_out (may be NULL) receives
+ * max ||A z|| / ||A||_est over the orthonormal basis vectors, with ||A||_est =
+ * max ||A x0|| / ||x0|| over the random vectors.
+ * Errors: LREP_EINVAL, LREP_ENOTCONV (that residual above tol: the operator
+ * is too ill-conditioned for the CG to separate N(A); the operator is then
+ * left without a null space), LREP_ENUMERIC (A zero or not finite),
+ * LREP_ENOTSPD, LREP_ENOMEM, LREP_EDEVICE. */
+int lrep_find_nullspace(lrep_op_t op, int64_t rmax, double tol, uint64_t seed, int64_t* r_out, double* res_out);
+
 /* Generalized LREP with a diagonal SPD metric (the remark on the generalized
  * LREP in Section 3.2; Example 4.5 has this form):
  *     K x = lambda B y,   M y = lambda B x,   B = diag(b), b_i > 0,

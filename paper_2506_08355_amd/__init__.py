@@ -122,6 +122,7 @@ _SIGS = {
     "lrep_create_callback": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_set_nullspace": (ctypes.c_int, [_P, _I64, _P, _I64, _I32]),
     "lrep_set_metric": (ctypes.c_int, [_P, _I64, _P, ctypes.c_uint32]),
+    "lrep_find_nullspace": (ctypes.c_int, [_P, _I64, _D, ctypes.c_uint64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lrep_destroy_op": (ctypes.c_int, [_P]),
     "lrep_solve": (ctypes.c_int, [_P, _I64, _I64, _I64, _D, ctypes.POINTER(lrep_solve_opts_t), _P, _P, _P, _I64,
                                   ctypes.POINTER(lrep_stats_t)]),
@@ -283,6 +284,16 @@ def lrep_set_nullspace(op, X0, ctx=None):
         return _check(lib().lrep_set_nullspace(op, 0, None, 1, 0), ctx, "lrep_set_nullspace")
     p, ld, dev = colmajor(X0)
     return _check(lib().lrep_set_nullspace(op, X0.shape[1], p, ld, int(dev)), ctx, "lrep_set_nullspace")
+
+
+def lrep_find_nullspace(op, rmax, tol=1e-10, seed=0, ctx=None):
+    """Compute and declare the null space of the semidefinite operator;
+    returns (r, residual) -- see lrep_find_nullspace in lrep.h."""
+    r = ctypes.c_int64(0)
+    res = ctypes.c_double(0.0)
+    _check(lib().lrep_find_nullspace(op, rmax, tol, seed, ctypes.byref(r), ctypes.byref(res)), ctx,
+           "lrep_find_nullspace")
+    return r.value, res.value
 
 
 def lrep_set_metric(op, b, ctx=None):

@@ -310,6 +310,17 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
     return rc;
 }
 
+int lrep_find_nullspace(lrep_op_t op, int64_t rmax, double tol, uint64_t seed, int64_t* r_out, double* res_out) {
+    if (!op || !r_out || rmax < 1 || rmax > 64 || rmax >= op->n || !(tol > 0)) return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    double res = 0.0;
+    *r_out = 0;
+    const int rc = find_nullspace(op, c->stream, rmax, tol, seed, r_out, &res);
+    if (res_out) *res_out = res;
+    return rc;
+}
+
 int lrep_set_metric(lrep_op_t op, int64_t n_b, const double* b, uint32_t flags) {
     if (!op || !b || n_b != op->n) return LREP_EINVAL;
     Ctx* c = op->ctx;

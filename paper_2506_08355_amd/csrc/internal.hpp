@@ -117,6 +117,11 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
 
 // Null-space preparation (solver.hip): X0t (device, n x r, ld n) -> op->X0, op->Y0.
 int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);
+// A basis of the null space of the semidefinite operator (at most rmax
+// columns), then prepare_nullspace on it; *r_out its dimension, *res_out the
+// largest ||A z|| / ||A||_est of the orthonormal basis vectors.
+int find_nullspace(Op* op, hipStream_t st, int64_t rmax, double tol, uint64_t seed, int64_t* r_out,
+                   double* res_out);
 
 // Operator apply with the roles (after a possible exchange): which = 0 -> "K", 1 -> "M".
 // With pq (low-rank operators, cols <= 32, op_apply_has_pq true), also

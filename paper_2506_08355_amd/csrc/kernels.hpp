@@ -177,6 +177,9 @@ hipError_t image_drift(hipStream_t st, int n, int cols, const double* A1, const 
                        const double* B2, int64_t ld, double* part, size_t part_elems, double* out);
 
 // out = in, column block copy with leading dimensions
+// C = A - B (n x cols)
+hipError_t sub_cols(hipStream_t st, int n, int cols, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc);
 hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out,
                      int64_t ldo);
 

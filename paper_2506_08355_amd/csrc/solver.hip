@@ -918,6 +918,96 @@ int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t) {
     return LREP_OK;
 }
 
+int find_nullspace(Op* op, hipStream_t st, int64_t rmax, double tol, uint64_t seed, int64_t* r_out,
+                   double* res_out) {
+    // N(A) of the symmetric positive semidefinite operator A (K, or M with the
+    // roles exchanged) by projecting random vectors (the remark on computing the
+    // generalized null space asks for the zero eigenvectors of A from a
+    // symmetric solver; this is the Krylov route to the same subspace).  CG on
+    // A x = A x0 from a zero start keeps its iterates in range(A) and converges
+    // to the range component of x0, so z = x0 - x is x0's component in N(A).
+    // The CG residual is A z itself.  Projections of rmax random vectors span
+    // N(A) when rmax >= dim N(A); block MGS (MGS-Biorth of (Z, Z)) orthonormalises
+    // them and drops those dependent on earlier ones.
+    if (rmax < 1 || rmax > 64 || rmax >= op->n || !(tol > 0)) return LREP_EINVAL;
+    Solver s;
+    s.op = op;
+    s.st = st;
+    s.n = op->n;
+    s.b = (int)rmax;
+    s.w = (int)rmax;
+    s.cap = 1;
+    s.nev = 1;
+    s.r0 = 0;
+    int rc = s.alloc();
+    if (rc != LREP_OK) return rc;
+    auto dev_fail = [&](hipError_t e, const char* what) { return s.dev_fail(e, what); };
+    const int n = (int)op->n, m = (int)rmax;
+    double* X0 = s.Ws.p;
+    double* Bv = s.rhs.p;
+    double* Z = s.Zs.p;
+    const int64_t ldg = 2 * kMaxD;
+    std::vector<double> gh((size_t)m * m);
+    // squared column norms of an n x k block (Gram diagonal)
+    auto sqnorms = [&](const double* A, int k, std::vector<double>& out) -> int {
+        CR(s.gram(s.segs({{A, (int64_t)n, k}}), s.segs({{A, (int64_t)n, k}}), s.G, ldg, 1));
+        CK(hipMemcpy2DAsync(gh.data(), (size_t)k * sizeof(double), s.G, ldg * sizeof(double), (size_t)k * sizeof(double),
+                            k, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        out.resize(k);
+        for (int j = 0; j < k; ++j) out[j] = gh[(size_t)j * k + j];
+        return LREP_OK;
+    };
+    CK(philox_normal(st, n, m, seed, X0, n));
+    CR(s.apply(0, X0, m, Bv));
+    std::vector<double> nx, nb, nz, nr;
+    CR(sqnorms(X0, m, nx));
+    CR(sqnorms(Bv, m, nb));
+    double normest = 0.0;   // max ||A x0|| / ||x0||, a lower estimate of ||A||_2
+    for (int j = 0; j < m; ++j) normest = std::max(normest, std::sqrt(nb[j] / nx[j]));
+    if (!(normest > 0) || !std::isfinite(normest)) {
+        op->ctx->set_error("find_nullspace: the semidefinite operator is zero or not finite");
+        return LREP_ENUMERIC;
+    }
+    const int maxit = (int)std::min<int64_t>(20 * (int64_t)n + 100, 200000);
+    CR(s.cg(0, Bv, m, 1e-15, maxit, true));
+    CK(sub_cols(st, n, m, X0, n, s.cgX.p, n, Z, n));
+    CR(sqnorms(Z, m, nz));
+    // a projection at rounding level carries no null direction (A definite on it)
+    int k = 0;
+    for (int j = 0; j < m; ++j)
+        if (std::sqrt(nz[j]) > 1e-8 * std::sqrt(nx[j])) CK(copy_cols(st, n, 1, Z + (size_t)j * n, n, Bv + (size_t)(k++) * n, n));
+    op->r0 = 0;
+    op->X0.release();
+    op->Y0.release();
+    *r_out = 0;
+    *res_out = 0.0;
+    if (k == 0) return LREP_OK;
+    CK(copy_cols(st, n, k, Bv, n, X0, n));
+    int kept = 0;
+    CR(s.block_mgs(Bv, X0, k, Bv, X0, &kept));
+    if (kept == 0) return LREP_OK;
+    // the orthonormal basis must satisfy ||A z|| <= tol ||A||
+    CR(s.apply(0, Bv, kept, Z));
+    CR(sqnorms(Z, kept, nr));
+    double worst = 0.0;
+    for (int j = 0; j < kept; ++j) worst = std::max(worst, std::sqrt(nr[j]) / normest);
+    *res_out = worst;
+    if (!(worst <= tol)) {
+        op->ctx->set_error("find_nullspace: the null-space basis reached ||A z|| / ||A|| = " + std::to_string(worst));
+        return LREP_ENOTCONV;
+    }
+    rc = prepare_nullspace(op, st, kept, Bv);
+    if (rc != LREP_OK) {
+        op->r0 = 0;
+        op->X0.release();
+        op->Y0.release();
+        return rc;
+    }
+    *r_out = kept;
+    return LREP_OK;
+}
+
 }  // namespace lrep
 
 namespace lrep {

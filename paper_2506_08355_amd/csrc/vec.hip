@@ -367,6 +367,14 @@ __global__ __launch_bounds__(NT) void copy_cols_kernel(int n, const double* __re
         out[(int64_t)j * ldo + i] = in[(int64_t)j * ldi + i];
 }
 
+__global__ __launch_bounds__(NT) void sub_cols_kernel(int n, const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ C, int64_t ldc) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        C[(int64_t)j * ldc + i] = A[(int64_t)j * lda + i] - B[(int64_t)j * ldb + i];
+}
+
 __global__ __launch_bounds__(1024) void max_offidentity_kernel(int d, const double* __restrict__ S, int64_t lds,
                                                                double* out) {
     __shared__ double red[1024 / WAVE];
@@ -614,6 +622,13 @@ hipError_t gs_rhs(hipStream_t st, int n, int w, const double* S, int64_t lds, co
 hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out, int64_t ldo) {
     if (cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, in, ldi, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t sub_cols(hipStream_t st, int n, int cols, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc) {
+    if (cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sub_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, A, lda, B, ldb, C, ldc);
     return hipGetLastError();
 }
 
