@@ -56,6 +56,8 @@ WORKLOADS = {
     # generalized LREP K x = lambda B y, M y = lambda B x with a diagonal metric B (growth direction f4)
     "dense8192metric": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                             metric_seed=1105),
+    "dense8192metricB": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                             metric_seed=1111, metric_dense=True),
 }
 
 
@@ -224,7 +226,10 @@ def describe(w):
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
         z += {0: "", 1: "; CG applies in BF16 (f32 accumulate)", 2: "; CG applies in FP16 (f32 accumulate)"}[
             w.get("precision", 0)]
-        if w.get("metric_seed"):
+        if w.get("metric_dense"):
+            z += ("; generalized LREP K x = lambda B y, M y = lambda B x, dense B = Q diag(beta) Q^T, Q Haar, "
+                  "beta log-uniform on [0.25, 4] (Cholesky reduction set up before the timed solves)")
+        elif w.get("metric_seed"):
             z += "; generalized LREP K x = lambda B y, M y = lambda B x, B = diag(b), b log-uniform on [0.25, 4]"
         return (f"dense FP64 n={w['n']}: K=Q1 diag(k) Q1^T, M=Q2 diag(m) Q2^T, Haar Q1/Q2, k,m~U[0.5,10]{z}; "
                 f"nev={w['nev']}, block={w['block']}, window={w['window']}, tol={w['tol']:g}")
@@ -310,9 +315,17 @@ def main():
     print(f"[bench] inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     ctx = L.lrep_init(0)
+    metric_setup_ms = None
     if w["kind"] == "dense":
         op = L.lrep_create_dense(ctx, Kd.T, Md.T, L.LREP_NULL_ON_M if w["zeros"] else 0)
-        if w.get("metric_seed"):
+        if w.get("metric_dense"):
+            Bmat = torch.from_numpy(np.ascontiguousarray(gen.metric_dense(n, w["metric_seed"]).T)).to(dev).T
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            L.lrep_set_metric_dense(op, Bmat, ctx)
+            metric_setup_ms = (time.perf_counter() - tm) * 1e3
+            print(f"[bench] dense metric set up in {metric_setup_ms:.1f} ms", file=sys.stderr, flush=True)
+        elif w.get("metric_seed"):
             bmetric = gen.metric_diag(n, w["metric_seed"])
             L.lrep_set_metric(op, bmetric, ctx)
         if w["zeros"]:
@@ -373,12 +386,19 @@ def main():
         if w.get("metric_seed"):
             # generalized pencil: residuals K x - lambda B y, M y - lambda B x over
             # (||H|| + lambda ||B||) ||(x, y)||, and Y^T B X = I
-            bd = torch.from_numpy(bmetric).to(dev)[:, None]
-            R1 = KX - (bd * Y) * lam[None, :]
-            R2 = MY - (bd * X) * lam[None, :]
+            if w.get("metric_dense"):
+                applyB = lambda V: Bmat @ V
+                normB = float(torch.linalg.matrix_norm(Bmat, 2))
+            else:
+                bd = torch.from_numpy(bmetric).to(dev)[:, None]
+                applyB = lambda V: bd * V
+                normB = float(bmetric.max())
+            BX, BY = applyB(X), applyB(Y)
+            R1 = KX - BY * lam[None, :]
+            R2 = MY - BX * lam[None, :]
             res = torch.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (
-                (normH + lam * float(bmetric.max())) * torch.sqrt((X ** 2).sum(0) + (Y ** 2).sum(0)))
-            biorth = float((Y.T @ (bd * X) - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max())
+                (normH + lam * normB) * torch.sqrt((X ** 2).sum(0) + (Y ** 2).sum(0)))
+            biorth = float((Y.T @ BX - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max())
         else:
             R1 = KX - Y * lam[None, :]
             R2 = MY - X * lam[None, :]
@@ -419,7 +439,16 @@ def main():
         except Exception:
             cores = os.cpu_count()
         print(f"[bench] CPU oracle sample: {args.cpu_iters} iterations ...", file=sys.stderr, flush=True)
-        if w["kind"] == "dense" and w.get("metric_seed"):
+        if w["kind"] == "dense" and w.get("metric_dense"):
+            # the transformed pencil L^-1 K L^-T, L^-1 M L^-T (B = L L^T) that the library solves
+            import scipy.linalg as sla
+            Lc = np.linalg.cholesky(Bmat.cpu().numpy())
+            def _tr(A):
+                T = sla.solve_triangular(Lc, A, lower=True)
+                T = sla.solve_triangular(Lc, T.T, lower=True)
+                return 0.5 * (T + T.T)
+            cop = oracle.DenseOperator(_tr(Kd.cpu().numpy()), _tr(Md.cpu().numpy()))
+        elif w["kind"] == "dense" and w.get("metric_seed"):
             # the scaled pencil S K S, S M S (S = B^-1/2) that the library solves
             sv = 1.0 / np.sqrt(bmetric)
             cop = oracle.DenseOperator(sv[:, None] * Kd.cpu().numpy() * sv[None, :],
@@ -454,6 +483,8 @@ def main():
                                        [round(v / args.steps, 2) for v in phase_ms])),
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if metric_setup_ms is not None:
+        out["metric_setup_ms"] = round(metric_setup_ms, 1)   # one-time, outside the timed solves
     L.lrep_destroy_op(op)
     L.lrep_finalize(ctx)
     print(json.dumps(out), flush=True)

@@ -31,7 +31,9 @@ Workloads (sizes and distributions follow the benchmark configurations):
            LREP K x = lambda B y, M y = lambda B x: log-uniform on [lo, hi]
            (default [0.25, 4]), a stand-in for a lumped finite-element mass
            matrix (the paper's Example 4.5 uses a P3 mass matrix, not
-           available here).  One draw of n uniforms.
+           available here).  One draw of n uniforms.  A dense SPD metric:
+           B = Q diag(beta) Q^T, Q Haar, beta log-uniform on [lo, hi]
+           (default [0.25, 4]); draws: Q (Gaussian n*n), beta (n).
 """
 from __future__ import annotations
 
@@ -50,6 +52,7 @@ __all__ = [
     "CasidaFactors",
     "dense_operator_device",
     "metric_diag",
+    "metric_dense",
 ]
 
 
@@ -211,3 +214,12 @@ def metric_diag(n: int, seed: int, lo: float = 0.25, hi: float = 4.0) -> np.ndar
     """Diagonal of the SPD metric B: exp(U[log lo, log hi]) per entry."""
     rng = np.random.default_rng(seed)
     return np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+
+
+def metric_dense(n: int, seed: int, lo: float = 0.25, hi: float = 4.0) -> np.ndarray:
+    """Dense SPD metric B = Q diag(beta) Q^T (symmetrised), Q Haar."""
+    rng = np.random.default_rng(seed)
+    Q = haar(n, rng)
+    beta = np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+    B = (Q * beta[None, :]) @ Q.T
+    return np.asfortranarray(0.5 * (B + B.T))

@@ -253,6 +253,25 @@ int lrep_find_nullspace(lrep_op_t op, int64_t rmax, double tol, uint64_t seed, i
  * finite), LREP_ENOMEM, LREP_EDEVICE. */
 int lrep_set_metric(lrep_op_t op, int64_t n, const double* b, uint32_t flags);
 
+/* The same generalized LREP with a dense SPD metric B (n x n, column-major,
+ * ld ldb >= n, host, or device with LREP_DEVICE_PTR; only its lower triangle
+ * is read), for dense operators.  With the Cholesky factor B = L L^T the
+ * pencil is the standard LREP of L^-1 K L^-T and L^-1 M L^-T in x^ = L^T x,
+ * y^ = L^T y, and Euclidean MGS-Biorth on (x^, y^) is MGS-Biorth in the B
+ * inner product on (x, y).  The library factors B on the device (blocked,
+ * 64-wide diagonal blocks), replaces its copies of K and M by the transformed
+ * (symmetrised) operators and keeps L^T and L^-T (2 n^2 doubles) for the
+ * coordinate changes; the one-time cost is about 6 n^3 flops on the MFMA
+ * products.  Null-space bases, start blocks and results are in the original
+ * coordinates as with lrep_set_metric, and the stopping rule measures
+ * ||L^-1 (K x - lambda B y)|| and ||L^-1 (M y - lambda B x)||.  The same
+ * preconditions as lrep_set_metric hold; low-rank and callback operators are
+ * refused.
+ * Errors: LREP_EINVAL (also when B is not positive definite: a Cholesky pivot
+ * is not positive; K and M are then unchanged), LREP_ENOMEM, LREP_EDEVICE (the
+ * operator may then be partly transformed and must be destroyed). */
+int lrep_set_metric_dense(lrep_op_t op, int64_t n, const double* B, int64_t ldb, uint32_t flags);
+
 /* Free an operator's device memory (borrowed arrays are not freed). */
 int lrep_destroy_op(lrep_op_t op);
 

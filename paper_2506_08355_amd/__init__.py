@@ -122,6 +122,7 @@ _SIGS = {
     "lrep_create_callback": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_set_nullspace": (ctypes.c_int, [_P, _I64, _P, _I64, _I32]),
     "lrep_set_metric": (ctypes.c_int, [_P, _I64, _P, ctypes.c_uint32]),
+    "lrep_set_metric_dense": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_uint32]),
     "lrep_find_nullspace": (ctypes.c_int, [_P, _I64, _D, ctypes.c_uint64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lrep_destroy_op": (ctypes.c_int, [_P]),
     "lrep_solve": (ctypes.c_int, [_P, _I64, _I64, _I64, _D, ctypes.POINTER(lrep_solve_opts_t), _P, _P, _P, _I64,
@@ -303,6 +304,16 @@ def lrep_set_metric(op, b, ctx=None):
         raise ValueError("b must be a vector")
     p, _, dev = colmajor(b)
     return _check(lib().lrep_set_metric(op, b.shape[0], p, LREP_DEVICE_PTR if dev else 0), ctx, "lrep_set_metric")
+
+
+def lrep_set_metric_dense(op, B, ctx=None):
+    """Dense SPD metric B (n x n, column-major NumPy array or device tensor;
+    its lower triangle is read) of a generalized LREP, for dense operators."""
+    if B.ndim != 2 or B.shape[0] != B.shape[1]:
+        raise ValueError("B must be square")
+    p, ld, dev = colmajor(B)
+    return _check(lib().lrep_set_metric_dense(op, B.shape[0], p, ld, LREP_DEVICE_PTR if dev else 0), ctx,
+                  "lrep_set_metric_dense")
 
 
 def lrep_destroy_op(op):

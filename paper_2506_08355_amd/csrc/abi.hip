@@ -298,9 +298,19 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
     if (rc != LREP_OK) return rc;
     hipError_t e = hipMemcpy2DAsync(tmp.p, op->n * sizeof(double), X0, ld * sizeof(double), op->n * sizeof(double), r,
                                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
-    // with a metric, N(S K S) = S^-1 N(K)
-    if (e == hipSuccess && op->Sv) e = metric_scale_rows(c->stream, op->n, (int)r, tmp.p, op->n, op->Sv, true);
     if (e != hipSuccess) return LREP_EDEVICE;
+    // with a metric B = C C^T the scaled operator's null space is C^T N(K)
+    if (op->has_metric()) {
+        DevBuf t2, wk;
+        const size_t welems = op->MetLT.p ? (size_t(8) << 20) : 0;
+        if (op->MetLT.p) {
+            rc = t2.alloc(c, (size_t)op->n * r * sizeof(double));
+            if (rc == LREP_OK) rc = wk.alloc(c, welems * sizeof(double));
+            if (rc != LREP_OK) return rc;
+        }
+        rc = op_metric_transform(op, c->stream, true, (int)r, tmp.p, op->n, t2.p, wk.p, welems);
+        if (rc != LREP_OK) return rc;
+    }
     rc = prepare_nullspace(op, c->stream, r, tmp.p);
     if (rc != LREP_OK) {
         op->r0 = 0;
@@ -330,7 +340,7 @@ int lrep_set_metric(lrep_op_t op, int64_t n_b, const double* b, uint32_t flags) 
         return LREP_EINVAL;
     };
     if (op->kind == 2) return refuse("lrep_set_metric: a callback operator applies the scaled pencil itself");
-    if (op->Sv) return refuse("lrep_set_metric: the operator already has a metric");
+    if (op->has_metric()) return refuse("lrep_set_metric: the operator already has a metric");
     if (op->r0 > 0) return refuse("lrep_set_metric: set the metric before the null space");
     const bool owned = op->kind == 0 ? (op->K == op->Kbuf.p && op->M == op->Mbuf.p)
                                      : (op->delta == op->dbuf.p && (op->rank == 0 || op->L == op->Lbuf.p));
@@ -379,6 +389,69 @@ int lrep_set_metric(lrep_op_t op, int64_t n_b, const double* b, uint32_t flags) 
     }
     op->Sbuf.take(sb);
     op->Sv = op->Sbuf.p;
+    return LREP_OK;
+}
+
+int lrep_set_metric_dense(lrep_op_t op, int64_t n_b, const double* B, int64_t ldb, uint32_t flags) {
+    if (!op || !B || n_b != op->n || ldb < op->n) return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    auto refuse = [&](const char* why) {
+        c->set_error(why);
+        return LREP_EINVAL;
+    };
+    if (op->kind != 0) return refuse("lrep_set_metric_dense: only dense operators keep their structure under a dense metric");
+    if (op->has_metric()) return refuse("lrep_set_metric_dense: the operator already has a metric");
+    if (op->r0 > 0) return refuse("lrep_set_metric_dense: set the metric before the null space");
+    if (!(op->K == op->Kbuf.p && op->M == op->Mbuf.p))
+        return refuse("lrep_set_metric_dense: the operator borrows the caller's arrays");
+    const int64_t n = op->n;
+    const size_t sq = (size_t)n * n * sizeof(double);
+    const size_t welems = size_t(8) << 20;
+    DevBuf Lb, Xb, LT, LinvT, Tb, Vall, Wb, Pt, wk, flag;
+    int rc = Lb.alloc(c, sq);
+    if (rc == LREP_OK) rc = Xb.alloc(c, sq);
+    if (rc == LREP_OK) rc = LT.alloc(c, sq);
+    if (rc == LREP_OK) rc = LinvT.alloc(c, sq);
+    if (rc == LREP_OK) rc = Tb.alloc(c, (size_t)n * 64 * sizeof(double));
+    if (rc == LREP_OK) rc = Vall.alloc(c, (size_t)n * 64 * sizeof(double) + 64 * 64 * sizeof(double));
+    if (rc == LREP_OK) rc = Wb.alloc(c, 64 * 64 * sizeof(double));
+    if (rc == LREP_OK) rc = Pt.alloc(c, (size_t)n * 64 * sizeof(double));
+    if (rc == LREP_OK) rc = wk.alloc(c, welems * sizeof(double));
+    if (rc == LREP_OK) rc = flag.alloc(c, sizeof(double));
+    if (rc != LREP_OK) return rc;
+    int* bad = reinterpret_cast<int*>(flag.p);
+    hipError_t e = hipMemcpy2DAsync(Lb.p, n * sizeof(double), B, ldb * sizeof(double), n * sizeof(double), n,
+                                    (flags & LREP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                    c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), c->stream);
+    if (e == hipSuccess)
+        e = metric_dense_setup(c->stream, n, Lb.p, Xb.p, Tb.p, LT.p, LinvT.p, Vall.p, Wb.p, Pt.p, wk.p, welems, bad);
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->set_error(hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    if (hbad) return refuse("lrep_set_metric_dense: B is not positive definite (Cholesky pivot <= 0)");
+    // K <- L^-1 K L^-T, M <- L^-1 M L^-T (Lb is free now: L^T is kept in LT)
+    e = metric_dense_apply(c->stream, n, op->K, op->ld, Xb.p, LinvT.p, Lb.p, wk.p, welems);
+    if (e == hipSuccess) e = metric_dense_apply(c->stream, n, op->M, op->ld, Xb.p, LinvT.p, Lb.p, wk.p, welems);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    {
+        std::lock_guard<std::mutex> lk(op->mu16);
+        op->prec16 = 0;
+        op->K16buf.release();
+        op->M16buf.release();
+    }
+    if (e != hipSuccess) {
+        // K and M may be partly transformed: the operator is no longer usable
+        c->set_error(std::string("lrep_set_metric_dense: ") + hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    op->MetLT.take(LT);
+    op->MetLinvT.take(LinvT);
     return LREP_OK;
 }
 

@@ -68,6 +68,10 @@ struct Op {
     // n values); the operator data above is already the scaled S K S, S M S
     DevBuf Sbuf;
     double* Sv = nullptr;
+    // dense SPD metric B = L L^T (dense operators): L^T and L^-T (n x n, ld n);
+    // the operator data is already L^-1 K L^-T, L^-1 M L^-T
+    DevBuf MetLT, MetLinvT;
+    bool has_metric() const { return Sv != nullptr || MetLT.p != nullptr; }
     // generalized null space, biorthonormal X0^T Y0 = I (roles already exchanged)
     int64_t r0 = 0;
     DevBuf X0, Y0;
@@ -117,6 +121,12 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
 
 // Null-space preparation (solver.hip): X0t (device, n x r, ld n) -> op->X0, op->Y0.
 int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);
+// Coordinate change of n x cols blocks for an operator with a metric B = C C^T:
+// to_hat x^ = C^T x, else x = C^-T x^ (in place; tmp n x cols, ld n, used by a
+// dense metric).  No-op without a metric.
+int op_metric_transform(Op* op, hipStream_t st, bool to_hat, int cols, double* X, int64_t ldx, double* tmp,
+                        double* work, size_t work_elems);
+
 // A basis of the null space of the semidefinite operator (at most rmax
 // columns), then prepare_nullspace on it; *r_out its dimension, *res_out the
 // largest ||A z|| / ||A||_est of the orthonormal basis vectors.

@@ -109,6 +109,15 @@ hipError_t metric_prepare(hipStream_t st, int64_t n, const double* b, double* s,
 hipError_t metric_scale_sym(hipStream_t st, int64_t n, double* A, int64_t ld, const double* s);
 // d <- s o s o d
 hipError_t metric_scale_diag(hipStream_t st, int64_t n, double* d, const double* s);
+// dense metric B (n x n, ld n, in Lb) = L L^T: L^T into LT, L^-T into LinvT,
+// L^-1 into Xb; Tb (n x 64), Vall (64 x n), Wb (64 x 64), Pt (64 x n) are
+// workspace; *bad = 1 when a pivot is not positive
+hipError_t metric_dense_setup(hipStream_t st, int64_t n, double* Lb, double* Xb, double* Tb, double* LT,
+                              double* LinvT, double* Vall, double* Wb, double* Pt, double* work, size_t work_elems,
+                              int* bad);
+// A (n x n, ld lda) <- Linv A Linv^T, symmetrised; Tb n x n workspace
+hipError_t metric_dense_apply(hipStream_t st, int64_t n, double* A, int64_t lda, const double* Linv,
+                              const double* LinvT, double* Tb, double* work, size_t work_elems);
 // X (n x cols, ld) <- diag(s) X, or diag(s)^-1 X with inverse
 hipError_t metric_scale_rows(hipStream_t st, int64_t n, int cols, double* X, int64_t ldx, const double* s,
                              bool inverse);

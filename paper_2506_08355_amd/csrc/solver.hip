@@ -447,7 +447,9 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             CK(hipMemcpy2DAsync(U0, n * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
                                 d0, hipMemcpyHostToDevice, st));
         // with a metric the start block is given in the original coordinates
-        if (op->Sv) CK(metric_scale_rows(st, n, d0, U0, n, op->Sv, true));
+        for (int c0 = 0; c0 < d0; c0 += kMaxD)
+            CR(op_metric_transform(op, st, true, std::min(kMaxD, d0 - c0), U0 + (size_t)c0 * n, n, tX.p, gwork.p,
+                                   GEMM_WORK_ELEMS));
     } else {
         CK(philox_normal(st, (int)n, d0, o.seed, U0, n));
     }
@@ -732,9 +734,11 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     if (c > 0) {
         double* OX = op->null_on_M() ? Yc.p : Xc.p;
         double* OY = op->null_on_M() ? Xc.p : Yc.p;
-        if (op->Sv) {   // back to the original coordinates: x = S x^, y = S y^
-            CK(metric_scale_rows(st, n, c, OX, n, op->Sv, false));
-            CK(metric_scale_rows(st, n, c, OY, n, op->Sv, false));
+        // with a metric B = C C^T, back to the original coordinates: x = C^-T x^, y = C^-T y^
+        for (int c0 = 0; c0 < c && op->has_metric(); c0 += kMaxD) {
+            const int cc = std::min(kMaxD, c - c0);
+            CR(op_metric_transform(op, st, false, cc, OX + (size_t)c0 * n, n, tX.p, gwork.p, GEMM_WORK_ELEMS));
+            CR(op_metric_transform(op, st, false, cc, OY + (size_t)c0 * n, n, tX.p, gwork.p, GEMM_WORK_ELEMS));
         }
         CK(sign_normalise(st, (int)n, c, OX, OY, n));
         const hipMemcpyKind kind = o.result_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;

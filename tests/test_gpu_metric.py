@@ -151,3 +151,94 @@ def test_metric_rejections_leave_the_operator_unchanged(ctx):
     with pytest.raises(L.LrepError):
         L.lrep_set_metric(op, good, ctx)
     L.lrep_destroy_op(op)
+
+
+@pytest.mark.parametrize("n", [256, 300, 2048])
+def test_dense_metric_matrix(ctx, n):
+    """A dense SPD metric B (Haar eigenvectors, eigenvalues log-uniform on
+    [0.25, 4]); n = 300 leaves a ragged last Cholesky block, n = 2048 runs the
+    panel and trailing updates on the tall-skinny products."""
+    nev, block, tol = 8, 16, 1e-10
+    print(f"[metric] dense B n={n}", flush=True)
+    K, M, f = gen.dense_operator(n, 1001 if n == 256 else 1020 + n)
+    B = gen.metric_dense(n, 1107)
+    U, _ = gen.init_block(n, 3 * block, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    L.lrep_set_metric_dense(op, B, ctx)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    ref = G.generalized_spectrum(K, M, B, nev)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+    normH = max(np.linalg.norm(K, 2), np.linalg.norm(M, 2))
+    res = G.generalized_residual(K, M, B, X, Y, lam, normH=normH, normB=np.linalg.norm(B, 2))
+    assert res.max() <= 1e-8, res.max()
+    assert G.b_biorth_error(B, X, Y) <= 1e-12
+
+
+def test_dense_metric_matrix_zero_variant_found_null_space(ctx):
+    n, nev, block, window, tol = 400, 24, 16, 8, 1e-10
+    print(f"[metric] dense B zero variant n={n}", flush=True)
+    K, M, f = gen.dense_operator(n, 1012, n_zero_m=8)
+    B = gen.metric_dense(n, 1108)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), L.LREP_NULL_ON_M)
+    L.lrep_set_metric_dense(op, dev_colmajor(B, torch), ctx)
+    r, res = L.lrep_find_nullspace(op, 16, 1e-10, 12, ctx)
+    assert r == 8 and res <= 1e-10
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    ref = G.generalized_spectrum(K, M, B, nev, zeros=8)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+    res = G.generalized_residual(K, M, B, X, Y, lam, normH=f.norm_H(), normB=np.linalg.norm(B, 2))
+    assert res.max() <= 1e-8, res.max()
+    assert G.b_biorth_error(B, X, Y) <= 1e-12
+    # n0 in N(M): 0 = n0^T M y = lambda n0^T B x
+    assert np.abs(f.null_basis_M().T @ (B @ X)).max() <= 1e-10
+
+
+def test_dense_metric_matrix_declared_null_space(ctx):
+    """The declared basis of N(M) in the original coordinates, with a dense B."""
+    n, nev, block, window, tol = 400, 24, 16, 8, 1e-10
+    K, M, f = gen.dense_operator(n, 1012, n_zero_m=8)
+    B = gen.metric_dense(n, 1109)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), L.LREP_NULL_ON_M)
+    L.lrep_set_metric_dense(op, B, ctx)
+    L.lrep_set_nullspace(op, np.asfortranarray(f.null_basis_M()), ctx)
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    np.testing.assert_allclose(lam, G.generalized_spectrum(K, M, B, nev, zeros=8), rtol=1e-10, atol=0)
+    assert G.b_biorth_error(B, X, Y) <= 1e-12
+
+
+def test_dense_metric_matrix_rejections(ctx):
+    n = 128
+    K, M, f = gen.dense_operator(n, 1001)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    B = gen.metric_dense(n, 1110)
+    Bbad = B.copy()
+    Bbad[70, 70] = -5.0                        # indefinite
+    with pytest.raises(L.LrepError) as e:
+        L.lrep_set_metric_dense(op, np.asfortranarray(Bbad), ctx)
+    assert e.value.code == L.LREP_EINVAL
+    lam = np.zeros(4)
+    X = np.zeros((n, 4), order="F")
+    Y = np.zeros((n, 4), order="F")
+    U, _ = gen.init_block(n, 24, 7)
+    rc, st = L.lrep_solve(op, n, 4, 8, 1e-10, L.make_opts(init=np.asfortranarray(U)), lam, X, Y, ctx=ctx,
+                          check=False)
+    assert rc == L.LREP_OK
+    from oracle import exact
+    np.testing.assert_allclose(lam, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, 4), rtol=1e-10)
+    L.lrep_set_metric_dense(op, B, ctx)
+    with pytest.raises(L.LrepError):
+        L.lrep_set_metric(op, gen.metric_diag(n, 1), ctx)      # one metric per operator
+    L.lrep_destroy_op(op)
+    fc = gen.casida_factors(n, 4, 3)
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(fc.delta, torch), dev_colmajor(fc.L, torch))
+    with pytest.raises(L.LrepError):
+        L.lrep_set_metric_dense(op, B, ctx)                    # low rank: refused
+    L.lrep_destroy_op(op)
