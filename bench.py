@@ -172,7 +172,7 @@ def serve(args, np, torch, gen, L):
                 k, nev, block, window = reqs[i]
                 op, n = pool[k]
                 lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
-                opts = L.make_opts(window=window, seed=17 + i)
+                opts = L.make_opts(window=window, seed=17 + i, graphs=args.graphs)
                 t = L.lrep_submit(ctx, op, nev, block, 1e-8, opts, lam, X, Y)
                 pending[t] = (i, time.perf_counter(), (lam, X, Y, opts))
                 i += 1
@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=0.0, help="serve: HBM budget of the context (0: none)")
     ap.add_argument("--rho", type=float, default=0.7,
                     help="serve: Poisson arrival rate as a fraction of the closed-loop solve rate")
+    ap.add_argument("--graphs", type=int, default=0, choices=[-1, 0, 1],
+                    help="Step 6 as a replayed HIP graph: 1 on, -1 off, 0 the library's default")
     ap.add_argument("--cpu-iters", type=int, default=40,
                     help="outer iterations of the CPU oracle in the bounded baseline sample (0: skip)")
     ap.add_argument("--operator-cache", default="", metavar="NPZ",
@@ -337,7 +339,8 @@ def main():
     Y = torch.zeros(nev, n, dtype=torch.float64, device=dev).T
 
     def step(profile):
-        opts = L.make_opts(window=window, init=U0d, profile=profile, precision=w.get("precision", 0))
+        opts = L.make_opts(window=window, init=U0d, profile=profile, precision=w.get("precision", 0),
+                           graphs=args.graphs)
         rc, st = L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx)
         return st
 

@@ -108,7 +108,14 @@ typedef struct lrep_solve_opts {
                               1e-2 tol, doubled below 1e-3 tol); images are always
                               fresh after a biorthogonality restoration and before
                               pairs are locked or returned.                           */
-    int32_t reserved;      /* must be 0                                                 */
+    int32_t graphs;        /* 1: Step 6 (right-hand sides, both CG solves, copies)
+                              as a HIP graph, captured once per block width and
+                              basis buffer and replayed; 0 (default) or -1: issued
+                              on the stream.  The replay issues all cg_maxit CG
+                              steps; steps after convergence return at once on the
+                              device flag.  Results are bitwise those of the
+                              stream path.  Ignored for callback operators and
+                              with profile.                                           */
 } lrep_solve_opts_t;
 
 /* Per-solve statistics (all optional to read). */

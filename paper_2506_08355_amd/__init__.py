@@ -67,7 +67,7 @@ class lrep_solve_opts_t(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("rebiorth_tol", ctypes.c_double),
         ("refresh", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 
@@ -323,8 +323,9 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0, profile=False, refresh=0, precision=0):
+              rebiorth_tol=0.0, profile=False, refresh=0, precision=0, graphs=0):
     o = lrep_solve_opts_t()
+    o.graphs = graphs
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
         p, ld, dev = colmajor(init)

@@ -102,7 +102,17 @@ struct Solver {
     DevBuf prof_log;
     static constexpr int kProfMax = 1 << 16;
 
+    // Step-6 graphs, one per (block width, basis buffer)
+    struct Step6Graph {
+        int nw;
+        const double* nx;
+        hipGraphExec_t exec;
+    };
+    std::vector<Step6Graph> graphs6;
+    bool capturing = false;
+
     ~Solver() {
+        for (auto& g : graphs6) (void)hipGraphExecDestroy(g.exec);
         if (hs) (void)hipHostFree(hs);
         if (note_h) (void)hipHostFree(note_h);
         for (auto e : prof_ev) (void)hipEventDestroy(e);
@@ -316,7 +326,7 @@ struct Solver {
         for (int it = 0; it < maxit; ++it) {
             // the device posts "no column active" for this solve: every step
             // not yet issued would return at once, so stop issuing them
-            if (it > 0) {
+            if (it > 0 && !capturing) {
                 const unsigned long long v = __atomic_load_n(note_h, __ATOMIC_ACQUIRE);
                 if ((v >> 1) == s.seq && (v & 1ull) == 0) break;
             }
@@ -431,6 +441,12 @@ struct Solver {
 int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) {
     auto t0 = std::chrono::steady_clock::now();
     const int d0 = b + 2 * w;
+    // Step 6 as a replayed graph (on request only: replays measured no faster
+    // than the stream path, whose small launches are bound by the device's
+    // kernel-to-kernel latency rather than by the host issuing them); not
+    // around a caller's function (it may synchronise) nor with per-launch
+    // profiling events
+    const bool use_graphs = op->kind != 2 && !o.profile && o.graphs == 1;
     int cur = 0, off = 0;
     int d = d0;
     // phases: 0 initialise U, V / 1 small-scale problem (applies, projection,
@@ -668,13 +684,43 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         }
         // Step 6: block Gauss-Seidel sweeps with CG
         mark(4);
-        for (int j = 0; j < o.ngs; ++j) {
-            CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, n, NX, NMY, n, wincol, lamw, rhs.p, n));
-            CR(cg(1, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
-            CK(copy_cols(st, (int)n, nw, cgX.p, n, Zs.p, n));
-            CK(gs_rhs(st, (int)n, nw, Zs.p, n, NY, NKX, n, wincol, lamw, rhs.p, n));
-            CR(cg(0, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
-            CK(copy_cols(st, (int)n, nw, cgX.p, n, Ws.p, n));
+        auto step6 = [&]() -> int {
+            for (int j = 0; j < o.ngs; ++j) {
+                CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, n, NX, NMY, n, wincol, lamw, rhs.p, n));
+                CR(cg(1, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
+                CK(copy_cols(st, (int)n, nw, cgX.p, n, Zs.p, n));
+                CK(gs_rhs(st, (int)n, nw, Zs.p, n, NY, NKX, n, wincol, lamw, rhs.p, n));
+                CR(cg(0, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
+                CK(copy_cols(st, (int)n, nw, cgX.p, n, Ws.p, n));
+            }
+            return LREP_OK;
+        };
+        if (use_graphs) {
+            // the launch sequence depends only on nw and on which of the two
+            // basis buffers is current: capture it once, replay it after
+            hipGraphExec_t ge = nullptr;
+            for (auto& g : graphs6)
+                if (g.nw == nw && g.nx == NX) ge = g.exec;
+            if (!ge) {
+                CK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                capturing = true;
+                const int rc6 = step6();
+                capturing = false;
+                hipGraph_t gr = nullptr;
+                const hipError_t ec = hipStreamEndCapture(st, &gr);
+                if (rc6 != LREP_OK) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return rc6;
+                }
+                CK(ec);
+                const hipError_t ei = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                CK(ei);
+                graphs6.push_back({nw, NX, ge});
+            }
+            CK(hipGraphLaunch(ge, st));
+        } else {
+            CR(step6());
         }
         // projection against [X0, Xc, X~_active, P~], applied twice
         const int kact = na + np;
@@ -845,7 +891,7 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.reserved != 0 || o.precision < 0 || o.precision > 2) return LREP_EINVAL;
+    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 2) return LREP_EINVAL;
     if (o.precision != 0 && op->kind == 0) {
         // 16-bit copies of K and M for the mixed-precision CG applies
         if (op->n % 8 != 0 || op->n < 64) return LREP_EINVAL;

@@ -224,3 +224,39 @@ def test_callback_error_ends_solve(ctx):
     L.lrep_destroy_op(op)
     assert rc == L.LREP_EDEVICE
     assert "callback" in L.lrep_last_error(ctx)
+
+
+@pytest.mark.parametrize("case", ["dense", "zero_variant", "lowrank", "bf16"])
+def test_step6_graph_replay_is_bitwise_the_stream_path(ctx, case):
+    """Step 6 captured as a HIP graph and replayed gives bitwise the results
+    of issuing the same launches on the stream (each replay reruns every CG
+    step; steps after convergence return at once on the device flag)."""
+    print(f"[graphs] {case}", flush=True)
+    if case == "lowrank":
+        n, nev, block, window, tol = 1500, 16, 16, 8, 1e-9
+        f = gen.casida_factors(n, 16, 1003)
+        make = lambda: L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    elif case == "zero_variant":
+        n, nev, block, window, tol = 400, 24, 16, 8, 1e-10
+        K, M, f = gen.dense_operator(n, 1012, n_zero_m=8)
+
+        def make():
+            op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch), L.LREP_NULL_ON_M)
+            L.lrep_set_nullspace(op, np.asfortranarray(f.null_basis_M()), ctx)
+            return op
+    else:
+        n, nev, block, window, tol = 256, 8, 16, 16, 1e-10
+        K, M, f = gen.dense_operator(n, 1001)
+        make = lambda: L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    out = []
+    for graphs in (-1, 1):
+        op = make()
+        rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U, graphs=graphs,
+                                      precision=1 if case == "bf16" else 0)
+        L.lrep_destroy_op(op)
+        assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+        out.append((lam, X, Y, st.iterations))
+    assert out[0][3] == out[1][3]
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
