@@ -135,3 +135,28 @@ def test_config2_full_size_metric(ctx):
     res = G.generalized_residual(K, M, B, X, Y, lam, normH=float(max(k.max(), m.max())), normB=float(b.max()))
     assert res.max() <= 1e-8, res.max()
     assert G.b_biorth_error(B, X, Y) <= 1e-12
+
+
+def test_config2_zero_variant_found_null_space(ctx):
+    """The zero variant at n = 8192 with N(M) computed on the device
+    (lrep_find_nullspace) instead of declared: the same bars as with the
+    declared basis, and X orthogonal to the true N(M)."""
+    n, nev, block, window, tol = 8192, 64, 64, 32, 1e-10
+    print(f"[fullsize] dense n={n} zero variant, found null space", flush=True)
+    Kd, Md, k, m, Q1, Q2 = gen.dense_operator_device(n, 1012, "cuda:0", n_zero_m=8, return_factors=True)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_dense(ctx, Kd.T, Md.T, L.LREP_NULL_ON_M)
+    r, res = L.lrep_find_nullspace(op, 16, 1e-10, 21, ctx)
+    assert r == 8 and res <= 1e-10, (r, res)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    K, M = Kd.cpu().numpy(), Md.cpu().numpy()
+    del Kd, Md
+    q2 = Q2.cpu().numpy()
+    ref = exact.dense_spectrum_smallest(Q1.cpu().numpy(), k, q2, m, nev)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+    res = h_residual(lambda v: K @ v, lambda v: M @ v, X, Y, lam, float(max(k.max(), m.max())))
+    assert res.max() <= 1e-8, res.max()
+    assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12
+    assert np.abs(q2[:, m == 0.0].T @ X).max() <= 1e-10
