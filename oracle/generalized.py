@@ -18,7 +18,7 @@ semidefinite and B symmetric positive definite.  The eigenpairs are unique
     det(lambda I - H) = det(lambda^2 I - K^ M^)); symmetric square-root
     factors from an eigendecomposition also cover singular K or M.
 
-A pair returned by a solver is judged by its own residuals K x - lambda B y,
+A pair returned by a solver is measured by its own residuals K x - lambda B y,
 M y - lambda B x and by the B-biorthogonality Y^T B X = I (the B inner
 product <u, v>_B = u^T B v that MGS-Biorth uses in the remark).
 """

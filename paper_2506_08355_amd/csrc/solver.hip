@@ -605,7 +605,7 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         int p = 0;
         while (p < nr && hs->eps[p] <= tol) ++p;
         if (carried > 0 && (p >= need || (p >= lock_unit && d > lock_unit))) {
-            // pairs are about to be locked or returned: judge them on images
+            // pairs are about to be locked or returned: test them on images
             // applied afresh to this subspace
             --it;
             need_fresh = true;
