@@ -579,8 +579,10 @@ hipError_t cg_alpha(hipStream_t st, int n, int w, const CgState& s) {
 size_t cg_pq_elems(int ntiles) { return (size_t)(ntiles + (ntiles + kFold - 1) / kFold) * 32; }
 
 hipError_t cg_update_tiles(hipStream_t st, int n, int w, int ntiles, double* pq, const CgState& s, double tol) {
-    if (ntiles > 2 * kFold) {
+    if (ntiles > 8 * kFold) {
         // every update block would otherwise walk the whole strided tile list
+        // (thousands of tiles at n = 262144; at n <= 65536 that walk costs less
+        // than the extra launch)
         const int nb = (ntiles + kFold - 1) / kFold;
         double* folded = pq + (size_t)ntiles * 32;
         hipLaunchKernelGGL(cg_fold_pq_kernel, dim3(nb), dim3(NT), 0, st, ntiles, pq, folded, s.any_active);
