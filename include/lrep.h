@@ -216,6 +216,15 @@ int lrep_create_callback(lrep_ctx_t ctx, int64_t n, lrep_apply_fn apply, void* u
  * Errors: LREP_EINVAL, LREP_ENOTSPD (X0~^T Y0~ not SPD), LREP_ENOMEM. */
 int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, int32_t on_device);
 
+/* Eigenvectors of the original problem [[A, B], [-B, -A]] [u; v] = lambda
+ * [u; v] from the returned pairs, by the change of variables of Section 1:
+ * U = Y + X, V = Y - X (each n x nev, column-major).  X, Y (ld ldxy) and
+ * U, V (ld lduv) are device arrays of the context's device; U and V must not
+ * overlap X or Y.  Blocking.
+ * Errors: LREP_EINVAL, LREP_EDEVICE. */
+int lrep_xy_to_uv(lrep_ctx_t ctx, int64_t n, int64_t nev, const double* X, const double* Y, int64_t ldxy, double* U,
+                  double* V, int64_t lduv);
+
 /* Compute the null space instead of declaring it (the remark on computing the
  * generalized null space, Section 2.2: the zero eigenvectors of the
  * semidefinite operator A = K, or M with LREP_NULL_ON_M).  rmax (1..64,

@@ -122,6 +122,7 @@ _SIGS = {
     "lrep_create_callback": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "lrep_set_nullspace": (ctypes.c_int, [_P, _I64, _P, _I64, _I32]),
     "lrep_set_metric": (ctypes.c_int, [_P, _I64, _P, ctypes.c_uint32]),
+    "lrep_xy_to_uv": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _P, _P, _I64]),
     "lrep_set_metric_dense": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_uint32]),
     "lrep_find_nullspace": (ctypes.c_int, [_P, _I64, _D, ctypes.c_uint64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lrep_destroy_op": (ctypes.c_int, [_P]),
@@ -304,6 +305,19 @@ def lrep_set_metric(op, b, ctx=None):
         raise ValueError("b must be a vector")
     p, _, dev = colmajor(b)
     return _check(lib().lrep_set_metric(op, b.shape[0], p, LREP_DEVICE_PTR if dev else 0), ctx, "lrep_set_metric")
+
+
+def lrep_xy_to_uv(ctx, X, Y, U, V):
+    """U = Y + X, V = Y - X for column-major device tensors (n x nev): the
+    eigenvectors of [[A, B], [-B, -A]] from those of H."""
+    px, ldx, dx = colmajor(X)
+    py, ldy, dy = colmajor(Y)
+    pu, ldu, du = colmajor(U)
+    pv, ldv, dv = colmajor(V)
+    if not (dx and dy and du and dv) or ldx != ldy or ldu != ldv or X.shape != Y.shape or U.shape != X.shape \
+            or V.shape != X.shape:
+        raise ValueError("X, Y, U, V must be device tensors of one shape, X/Y and U/V with equal leading dimensions")
+    return _check(lib().lrep_xy_to_uv(ctx, X.shape[0], X.shape[1], px, py, ldx, pu, pv, ldu), ctx, "lrep_xy_to_uv")
 
 
 def lrep_set_metric_dense(op, B, ctx=None):

@@ -320,6 +320,21 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
     return rc;
 }
 
+int lrep_xy_to_uv(lrep_ctx_t c, int64_t n, int64_t nev, const double* X, const double* Y, int64_t ldxy, double* U,
+                  double* V, int64_t lduv) {
+    if (!c || n < 1 || nev < 0 || n > (int64_t)INT32_MAX || nev > 65535 || ldxy < n || lduv < n || !X || !Y || !U ||
+        !V)
+        return LREP_EINVAL;
+    if (set_device(c) != LREP_OK) return LREP_EDEVICE;
+    hipError_t e = xy_to_uv(c->stream, (int)n, (int)nev, X, Y, ldxy, U, V, lduv);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->set_error(hipGetErrorString(e));
+        return LREP_EDEVICE;
+    }
+    return LREP_OK;
+}
+
 int lrep_find_nullspace(lrep_op_t op, int64_t rmax, double tol, uint64_t seed, int64_t* r_out, double* res_out) {
     if (!op || !r_out || rmax < 1 || rmax > 64 || rmax >= op->n || !(tol > 0)) return LREP_EINVAL;
     Ctx* c = op->ctx;

@@ -186,6 +186,9 @@ hipError_t image_drift(hipStream_t st, int n, int cols, const double* A1, const 
                        const double* B2, int64_t ld, double* part, size_t part_elems, double* out);
 
 // out = in, column block copy with leading dimensions
+// U = Y + X, V = Y - X (n x cols)
+hipError_t xy_to_uv(hipStream_t st, int n, int cols, const double* X, const double* Y, int64_t ldxy, double* U,
+                    double* V, int64_t lduv);
 // C = A - B (n x cols)
 hipError_t sub_cols(hipStream_t st, int n, int cols, const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C, int64_t ldc);

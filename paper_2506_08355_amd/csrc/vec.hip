@@ -375,6 +375,18 @@ __global__ __launch_bounds__(NT) void sub_cols_kernel(int n, const double* __res
         C[(int64_t)j * ldc + i] = A[(int64_t)j * lda + i] - B[(int64_t)j * ldb + i];
 }
 
+// U = Y + X, V = Y - X (n x cols)
+__global__ __launch_bounds__(NT) void xy_to_uv_kernel(int n, const double* __restrict__ X, const double* __restrict__ Y,
+                                                      int64_t ldxy, double* __restrict__ U, double* __restrict__ V,
+                                                      int64_t lduv) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const double x = X[(int64_t)j * ldxy + i], y = Y[(int64_t)j * ldxy + i];
+        U[(int64_t)j * lduv + i] = y + x;
+        V[(int64_t)j * lduv + i] = y - x;
+    }
+}
+
 __global__ __launch_bounds__(1024) void max_offidentity_kernel(int d, const double* __restrict__ S, int64_t lds,
                                                                double* out) {
     __shared__ double red[1024 / WAVE];
@@ -624,6 +636,13 @@ hipError_t gs_rhs(hipStream_t st, int n, int w, const double* S, int64_t lds, co
 hipError_t copy_cols(hipStream_t st, int n, int cols, const double* in, int64_t ldi, double* out, int64_t ldo) {
     if (cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_cols_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, in, ldi, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t xy_to_uv(hipStream_t st, int n, int cols, const double* X, const double* Y, int64_t ldxy, double* U,
+                    double* V, int64_t lduv) {
+    if (cols <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(xy_to_uv_kernel, grid_rows(n, cols, 256), dim3(NT), 0, st, n, X, Y, ldxy, U, V, lduv);
     return hipGetLastError();
 }
 

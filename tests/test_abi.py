@@ -36,6 +36,7 @@ def test_invalid_arguments_are_rejected_without_device_work():
     assert lib.lrep_set_metric(None, 10, None, 0) == L.LREP_EINVAL
     assert lib.lrep_find_nullspace(None, 4, 1e-10, 0, None, None) == L.LREP_EINVAL
     assert lib.lrep_set_metric_dense(None, 10, None, 10, 0) == L.LREP_EINVAL
+    assert lib.lrep_xy_to_uv(None, 10, 1, None, None, 10, None, None, 10) == L.LREP_EINVAL
 
 
 def test_binding_layout_checks():

@@ -260,3 +260,29 @@ def test_step6_graph_replay_is_bitwise_the_stream_path(ctx, case):
     assert out[0][3] == out[1][3]
     for a, b in zip(out[0][:3], out[1][:3]):
         assert np.array_equal(a, b)
+
+
+def test_xy_to_uv_solves_the_original_problem(ctx):
+    """u = y + x, v = y - x (Section 1) solve [[A, B], [-B, -A]] [u; v] =
+    lambda [u; v] with A = (K + M) / 2, B = (M - K) / 2."""
+    n, nev, block, tol = 256, 8, 16, 1e-10
+    K, M, f = gen.dense_operator(n, 1001)
+    U0, _ = gen.init_block(n, 3 * block, 7)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    lam = torch.zeros(nev, dtype=torch.float64, device="cuda:0")
+    X = torch.zeros(nev, n, dtype=torch.float64, device="cuda:0").T
+    Y = torch.zeros(nev, n, dtype=torch.float64, device="cuda:0").T
+    opts = L.make_opts(init=np.asfortranarray(U0), result_on_device=True)
+    L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx)
+    L.lrep_destroy_op(op)
+    Ud = torch.zeros(nev, n, dtype=torch.float64, device="cuda:0").T
+    Vd = torch.zeros(nev, n, dtype=torch.float64, device="cuda:0").T
+    L.lrep_xy_to_uv(ctx, X, Y, Ud, Vd)
+    u, v, x, y, lm = (t.cpu().numpy() for t in (Ud, Vd, X, Y, lam))
+    np.testing.assert_array_equal(u, y + x)
+    np.testing.assert_array_equal(v, y - x)
+    A, B = 0.5 * (K + M), 0.5 * (M - K)
+    R1 = A @ u + B @ v - u * lm
+    R2 = -B @ u - A @ v - v * lm
+    res = np.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (f.norm_H() * np.sqrt((u ** 2).sum(0) + (v ** 2).sum(0)))
+    assert res.max() <= 1e-8, res.max()
