@@ -73,6 +73,7 @@ void worker_main(Ctx* c) {
         lk.unlock();
         lrep_stats_t stats{};
         int rc;
+        bool retried_alone = false;
         for (;;) {
             rc = solve(t.op, st, t.req.nev, t.req.block, t.req.tol, &t.req.opts, t.req.lambda, t.req.X, t.req.Y,
                        t.req.ldxy, &stats);
@@ -82,7 +83,14 @@ void worker_main(Ctx* c) {
             bool others = false;
             for (auto& kv : c->tickets)
                 if (kv.first != id && kv.second.state == 1) others = true;
-            if (!others) break;
+            if (!others) {
+                // the requests that held the memory may have finished (and freed
+                // it) after this attempt failed: try once more before giving up
+                if (retried_alone) break;
+                retried_alone = true;
+                continue;
+            }
+            retried_alone = false;
             c->q_cv.wait_for(l2, std::chrono::milliseconds(20));
         }
         lk.lock();

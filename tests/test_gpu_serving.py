@@ -116,7 +116,9 @@ def test_budget_admission_queues_and_matches():
     for op in ops:
         L.lrep_destroy_op(op)
     L.lrep_finalize(probe)
-    op_bytes = sum(2 * n * n * 8 for n in sizes[:2]) + 16384 * 65 * 8 + 20000 * 101 * 8
+    # dense K, M; low-rank delta and L plus the row-major copy of L (rank rounded up to 64)
+    op_bytes = (sum(2 * n * n * 8 for n in sizes[:2]) + 16384 * 65 * 8 + 20000 * 101 * 8
+                + 16384 * 64 * 8 + 20000 * 128 * 8)
     budget = op_bytes + 400 * (1 << 20)   # the largest solve needs about 300 MiB
     ctx = L.lrep_init(0, budget)
     ops, sizes = make_ops(ctx)
