@@ -110,9 +110,11 @@ struct Solver {
     };
     std::vector<Step6Graph> graphs6;
     bool capturing = false;
+    hipEvent_t np_ev = nullptr;   // Step 5's status copy has landed
 
     ~Solver() {
         for (auto& g : graphs6) (void)hipGraphExecDestroy(g.exec);
+        if (np_ev) (void)hipEventDestroy(np_ev);
         if (hs) (void)hipHostFree(hs);
         if (note_h) (void)hipHostFree(note_h);
         for (auto e : prof_ev) (void)hipEventDestroy(e);
@@ -267,6 +269,7 @@ struct Solver {
         napplies = reinterpret_cast<unsigned long long*>(tickets + 8);
         CK(hipMemsetAsync(ismall.p, 0, ismall.bytes, st));
         CK(hipHostMalloc((void**)&hs, sizeof(HostStatus), hipHostMallocDefault));
+        CK(hipEventCreateWithFlags(&np_ev, hipEventDisableTiming));
         CK(hipHostMalloc((void**)&note_h, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent));
         *note_h = 0;
         CK(hipHostGetDevicePointer((void**)&note_d, note_h, 0));
@@ -668,20 +671,12 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         // Step 5
         mark(3);
         CK(step5_pq(st, d, hi, Xh, Yh, win, nw, Ph, Qh, scr, status, MGS_COS_TOL, MGS_DEP_TOL, gwork.p, GEMM_WORK_ELEMS));
-        CR(read_status());
-        const int np = hs->status[ST_NP];
-        stats.mgs_drops += nw - np;
-        double* Pt = NX + (size_t)hi * n;
-        double* Qt = NY + (size_t)hi * n;
-        // the next subspace's images are carried whenever carrying is on, also
-        // into a refresh, where they are compared with the fresh ones
-        const bool carry_next = interval > 1;
-        {
-            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
-            const double* B4[4] = {Ph, Qh, Ph, Qh};
-            double* C4[4] = {Pt, Qt, NKX + (size_t)hi * n, NMY + (size_t)hi * n};
-            CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, n, 1.0, 0.0));
-        }
+        // the number np of kept P~ columns is first needed after Step 6's CG
+        // (which reads only window columns, below hi or from hi + 2w, and
+        // writes only the CG buffers): fetch it behind an event and wait for it
+        // while the CG runs, instead of draining the stream here
+        CK(hipMemcpyAsync(hs->status, status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, st));
+        CK(hipEventRecord(np_ev, st));
         // Step 6: block Gauss-Seidel sweeps with CG
         mark(4);
         auto step6 = [&]() -> int {
@@ -721,6 +716,21 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
             CK(hipGraphLaunch(ge, st));
         } else {
             CR(step6());
+        }
+        CK(hipEventSynchronize(np_ev));
+        const int np = hs->status[ST_NP];
+        stats.mgs_drops += nw - np;
+        double* Pt = NX + (size_t)hi * n;
+        double* Qt = NY + (size_t)hi * n;
+        // the next subspace's images are carried whenever carrying is on, also
+        // into a refresh, where they are compared with the fresh ones
+        const bool carry_next = interval > 1;
+        {
+            // P~ = U P^, Q~ = V Q^ (Step 5), into columns [hi, hi + np) of the next basis
+            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+            const double* B4[4] = {Ph, Qh, Ph, Qh};
+            double* C4[4] = {Pt, Qt, NKX + (size_t)hi * n, NMY + (size_t)hi * n};
+            CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, n, 1.0, 0.0));
         }
         // projection against [X0, Xc, X~_active, P~], applied twice
         const int kact = na + np;
