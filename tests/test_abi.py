@@ -49,3 +49,33 @@ def test_binding_layout_checks():
     t = torch.zeros(3, 5, dtype=torch.float64).T
     p, ld, dev = L.colmajor(t)
     assert ld == 5 and not dev
+
+
+def test_headers_are_c99_and_layouts_match_the_binding(tmp_path):
+    """tests/abi_check.c includes both headers as plain C99 (-pedantic, no
+    warnings), links the library and prints the struct layouts, which must
+    match the ctypes mirrors."""
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.dirname(L.LIB_PATH)
+    exe = str(tmp_path / "abi_check")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I" + os.path.join(root, "include"), os.path.join(root, "tests", "abi_check.c"),
+                        "-o", exe, "-L" + libdir, "-llrep", "-Wl,-rpath," + libdir,
+                        "-Wl,--allow-shlib-undefined"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    f = r.stdout.split()
+    vals = dict(zip(f[0::2], (int(v) for v in f[1::2])))
+    assert vals["opts"] == ctypes.sizeof(L.lrep_solve_opts_t)
+    assert vals["stats"] == ctypes.sizeof(L.lrep_stats_t)
+    assert vals["request"] == ctypes.sizeof(L.lrep_request_t)
+    assert vals["graphs"] == L.lrep_solve_opts_t.graphs.offset
+    assert vals["precision"] == L.lrep_solve_opts_t.precision.offset
+    assert vals["init_U"] == L.lrep_solve_opts_t.init_U.offset
