@@ -191,7 +191,12 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
                                                       const int* __restrict__ flag) {
     if (flag && *flag == 0) return;
     const int lane = threadIdx.x, c = lane % 16, g = lane / 16;
-    const int row0 = blockIdx.x * RW;
+    // tiles in reverse launch order: the first pass has just streamed L from
+    // the first row to the last, so the last rows are the ones still in the
+    // MALL; ending at row 0 in turn hands the first rows to the next first
+    // pass (3-4 % on each pass)
+    const int tile = gridDim.x - 1 - blockIdx.x;
+    const int row0 = tile * RW;
     // rows beyond n read row n - 1; those outputs are not written
     const double* ap[4];
 #pragma unroll
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
                 v += __shfl_xor(v, 2, WAVE);
                 v += __shfl_xor(v, 4, WAVE);
                 v += __shfl_xor(v, 8, WAVE);
-                if (c == 0) pq[(int64_t)blockIdx.x * 32 + 16 * u + 4 * r + g] = v;
+                if (c == 0) pq[(int64_t)tile * 32 + 16 * u + 4 * r + g] = v;
             }
     }
 }
