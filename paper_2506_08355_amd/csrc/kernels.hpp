@@ -130,6 +130,11 @@ hipError_t diag_scale(hipStream_t st, int n, int cols, const double* delta,
 // t of X[:, j] Y[:, j] (the CG's p . A p per tile)
 hipError_t diag_scale_pq(hipStream_t st, int n, int cols, const double* delta, const double* X, int64_t ldx,
                          double* Y, int64_t ldy, double* pq, const int* active_flag = nullptr);
+// the same on CG vectors (ld n) with the pending direction update folded in:
+// P = R + beta P for the active columns first (as cg_direction), then Q, pq
+hipError_t diag_dir_scale_pq(hipStream_t st, int n, int cols, const double* delta, double* P, const double* R,
+                             const double* beta, const int* active, double* Q, double* pq,
+                             const int* active_flag = nullptr);
 
 // Step-4 residuals.  For Ritz columns j in [0, cols):
 //   eps[j] = sqrt(|KX_j - l_j Y_j|^2 + |MY_j - l_j X_j|^2) / ((1 + l_j) sqrt(|X_j|^2 + |Y_j|^2))

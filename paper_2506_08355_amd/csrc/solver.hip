@@ -320,6 +320,7 @@ struct Solver {
         const int ntiles = (int)stream_tiles((int)n);
         // low-rank operators: the apply also returns p.q per 64-row tile
         const bool lr_pq = !Ad && op_apply_has_pq(op, which, cgP.p, n, nw);
+        const bool lr_diag = lr_pq && ((which == 0) != op->null_on_M());   // K = diag(delta)
         // mixed precision: the product on the 16-bit operator copy
         const uint16_t* A16 = nullptr;
         if (Ad && o.precision != 0 && op->prec16 == o.precision) {
@@ -347,6 +348,15 @@ struct Solver {
                 // direction update of the previous step, pack, apply, p.q per tile
                 CK(cg_dense_apply(st, (int)n, nw, Ad, op->ld, cgP.p, cgR.p, cg_beta, cg_active, it == 0 ? 1 : 0,
                                   cgQ.p, cg_pq, gwork.p, GEMM_WORK_ELEMS, cg_any, ev, logslot));
+                CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
+            } else if (lr_diag) {
+                // diagonal K of a low-rank operator: the direction update of the
+                // previous step is folded into this step's apply
+                if (it == 0)
+                    CK(diag_scale_pq(st, (int)n, nw, op->delta, cgP.p, n, cgQ.p, n, cg_pq, cg_any));
+                else
+                    CK(diag_dir_scale_pq(st, (int)n, nw, op->delta, cgP.p, cgR.p, cg_beta, cg_active, cgQ.p, cg_pq,
+                                         cg_any));
                 CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
             } else if (lr_pq) {
                 CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev, cg_pq));

@@ -53,6 +53,39 @@ __global__ __launch_bounds__(NT) void diag_scale_pq_kernel(int n, int cols, cons
     }
 }
 
+// the same with the CG's pending direction update folded in: for the active
+// columns p = r + beta p (written back), then q = delta o p and the tile sums
+// of p . q; the arithmetic of each entry is that of cg_direction_kernel
+__global__ __launch_bounds__(NT) void diag_dir_scale_pq_kernel(int n, int cols, const double* __restrict__ delta,
+                                                               double* __restrict__ P, const double* __restrict__ R,
+                                                               const double* __restrict__ beta,
+                                                               const int* __restrict__ active,
+                                                               double* __restrict__ Q, double* __restrict__ pq,
+                                                               const int* __restrict__ active_flag) {
+    if (active_flag && *active_flag == 0) return;
+    const int i = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const int row = blockIdx.x * 64 + i;
+    const double dv = row < n ? delta[row] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int col = grp * 8 + u;
+        double s = 0.0;
+        if (col < cols && row < n) {
+            const int64_t o = (int64_t)col * n + row;
+            double x = P[o];
+            if (active[col]) {
+                x = R[o] + beta[col] * x;
+                P[o] = x;
+            }
+            const double y = dv * x;
+            Q[o] = y;
+            s = x * y;
+        }
+        s = wave_sum(s);
+        if (i == 0 && col < cols) pq[(int64_t)blockIdx.x * 32 + col] = s;
+    }
+}
+
 // ---------------------------------------------------------------- residuals
 __global__ __launch_bounds__(NT) void residual_kernel(int n, int cols, int nchunks, const double* __restrict__ X,
                                                       const double* __restrict__ Y, const double* __restrict__ KX,
@@ -505,6 +538,15 @@ hipError_t diag_scale_pq(hipStream_t st, int n, int cols, const double* delta, c
     if (cols > 32) return hipErrorInvalidValue;
     hipLaunchKernelGGL(diag_scale_pq_kernel, dim3((n + 63) / 64), dim3(NT), 0, st, n, cols, delta, X, ldx, Y, ldy, pq,
                        active_flag);
+    return hipGetLastError();
+}
+
+hipError_t diag_dir_scale_pq(hipStream_t st, int n, int cols, const double* delta, double* P, const double* R,
+                             const double* beta, const int* active, double* Q, double* pq, const int* active_flag) {
+    if (cols <= 0) return hipSuccess;
+    if (cols > 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_dir_scale_pq_kernel, dim3((n + 63) / 64), dim3(NT), 0, st, n, cols, delta, P, R, beta,
+                       active, Q, pq, active_flag);
     return hipGetLastError();
 }
 
