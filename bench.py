@@ -6,24 +6,31 @@ applies, Rayleigh-Ritz projection and small LREP, residuals, P/Q update, CG
 search directions, MGS-Biorth against the converged and active blocks) on a
 device-resident operator, from the same seeded starting block each step.
 
-Default workload: dense FP64, n = 8192, K = Q1 diag(k) Q1^T, M = Q2 diag(m)
-Q2^T with Haar Q1, Q2 (seed 1002) and k, m ~ U[0.5, 10]; the 64 smallest
-positive eigenpairs, block 64, window 32 (moving mechanism), tolerance 1e-10.
-value = eigenpairs per second over the timed steps.
+Default workload: the matrix-free Casida-style operator, FP64, n = 262144:
+K = diag(delta), M = diag(delta) + 2 L L^T, delta ~ U[0.1, 20] sorted, L an
+n x 256 Gaussian matrix scaled by 1/sqrt(n) (seed 1003); the 128 smallest
+positive eigenpairs at residual tolerance 1e-8, block 64, window 32 (moving
+mechanism).  value = eigenpairs per second over the timed steps, which run
+with every profiling hook off.  `--workload dense8192` selects the dense
+n = 8192 workload (tolerance 1e-10) and the others listed in WORKLOADS.
 
-Also reported on the same JSON line:
-  roofline      the dominant kernel (apply_stream_kernel, the FP64 MFMA block
-                apply of the CG inner solves, w = 32 columns) timed live with
-                HIP events on the solve's stream; algorithmic bytes
-                8 n^2 + 16 n w per launch against the 8 TB/s HBM peak.
-                `traffic` is the HBM bytes per launch measured with hardware
-                counters (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by
-                the same counters on a plain copy of known size), read from
-                the committed profile summary, and null when the kernel
-                source has changed since the counters were taken;
-  cpu_baseline  the FP64 CPU oracle on the same operator for a bounded number
-                of outer iterations, scaled to eigenpairs/s by the number of
-                iterations the GPU solve needed.
+Also reported on the same JSON line, from one extra profiled solve after the
+timed region:
+  roofline      the dominant kernel (the low-rank M apply of the CG inner
+                solves for the Casida workload, the FP64 MFMA streaming block
+                apply for the dense ones) timed live with HIP events on the
+                solve's stream; its algorithmic bytes per launch against the
+                8 TB/s HBM peak.  `traffic` is the HBM bytes per launch
+                measured with hardware counters (rocprofv3 --pmc FETCH_SIZE /
+                WRITE_SIZE, scaled by the same counters on a plain copy of
+                known size), read from the committed profile summary, and
+                null when the kernel source has changed since the counters
+                were taken;
+  phases        per-phase GPU time of that solve in the paper's five buckets;
+  cpu_baseline  the FP64 CPU oracle on the same operator and start block,
+                to convergence where that takes a minute or less on the host,
+                else for a bounded number of outer iterations scaled to the
+                iteration count of the GPU solve (the line says which).
 """
 import argparse
 import hashlib
@@ -42,17 +49,20 @@ WORKLOADS = {
     "dense8192": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0),
     "dense8192z": dict(kind="dense", n=8192, seed=1012, nev=64, block=64, window=32, tol=1e-10, zeros=8),
     "dense256": dict(kind="dense", n=256, seed=1001, nev=8, block=16, window=16, tol=1e-10, zeros=0),
-    "dense32768": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0),
+    "dense32768": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                       cpu_iters=4),
     # mixed precision (growth direction 1): BF16 / FP16 operator copies for the CG applies
     "dense32768bf16": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
-                           precision=1),
+                           precision=1, cpu_iters=4),
     "dense32768fp16": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
-                           precision=2),
+                           precision=2, cpu_iters=4),
     "dense8192bf16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                           precision=1),
     "dense8192fp16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                           precision=2),
-    "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8),
+    # one oracle iteration takes about a minute on the host: the baseline is a bounded sample
+    "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8,
+                         cpu_iters=1),
     # generalized LREP K x = lambda B y, M y = lambda B x with a diagonal metric B (growth direction f4)
     "dense8192metric": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                             metric_seed=1105),
@@ -61,24 +71,33 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_stream_kernel.dense8192.traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_08355_amd", "csrc", "apply.hip")
+# counter summaries of the dominant kernel, per workload: file, kernel source
+# the counters were taken on, and the key under which its SHA-256 is stored
+TRAFFIC = {
+    "dense8192": ("apply_stream_kernel.dense8192.traffic.md", "apply.hip", "apply_hip_sha256"),
+    "casida262144": ("lowrank_cg.casida262144.traffic.md", "lowrank.hip", "lowrank_hip_sha256"),
+}
+CSRC = os.path.join(ROOT, "paper_2506_08355_amd", "csrc")
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the streaming apply from the committed counter
-    summary, if it was taken on this workload and on the current source."""
-    if workload != "dense8192" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if one was taken on this workload and on the current source."""
+    if workload not in TRAFFIC:
+        return None
+    fname, src, key = TRAFFIC[workload]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    with open(KERNEL_SOURCE, "rb") as fh:
+    with open(os.path.join(CSRC, src), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()
-    if fields.get("apply_hip_sha256") != sha:
+    if fields.get(key) != sha:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -243,7 +262,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dense8192", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="casida262144", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--serve-sizes", choices=["reduced", "full"], default="reduced",
                     help="serve: operator size ranges (full: dense n <= 16384, low-rank n <= 262144)")
@@ -252,8 +271,9 @@ def main():
                     help="serve: Poisson arrival rate as a fraction of the closed-loop solve rate")
     ap.add_argument("--graphs", type=int, default=0, choices=[-1, 0, 1],
                     help="Step 6 as a replayed HIP graph: 1 on, -1 off, 0 the library's default")
-    ap.add_argument("--cpu-iters", type=int, default=40,
-                    help="outer iterations of the CPU oracle in the bounded baseline sample (0: skip)")
+    ap.add_argument("--cpu-iters", type=int, default=-1,
+                    help="outer iterations of the CPU oracle baseline (0: skip; -1: the workload's default, "
+                         "to convergence where that takes about a minute on the host, else a bounded sample)")
     ap.add_argument("--operator-cache", default="", metavar="NPZ",
                     help="dense workloads: load K, M from this .npz if it exists, else generate and save them "
                          "(lets profiler passes skip the device QR of the generator)")
@@ -349,22 +369,13 @@ def main():
         print(f"[bench] warmup {i}: {st.time_ms:.1f} ms, {st.iterations} iterations", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     lat = []
-    prof_ms = prof_bytes = prof_flops = 0.0
-    prof_launches = 0
-    phase_ms = [0.0] * 5
     iters = 0
     restores = 0
     t_start = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        st = step(True)
+        st = step(False)
         lat.append((time.perf_counter() - ts) * 1e3)
-        prof_ms += st.prof_ms
-        prof_bytes += st.prof_bytes
-        prof_flops += st.prof_flops
-        prof_launches += st.prof_launches
-        for k in range(5):
-            phase_ms[k] += st.phase_ms[k]
         iters = st.iterations
         restores = st.rebiorth
         print(f"[bench] step {i}: {lat[-1]:.1f} ms, {st.iterations} iterations, {st.rebiorth} restores, "
@@ -372,6 +383,17 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     value = nev * args.steps / total
+
+    # one profiled solve outside the timed region: HIP events around every CG
+    # apply and at the phase boundaries (the roofline and the phase split)
+    tp = time.perf_counter()
+    st = step(True)
+    torch.cuda.synchronize()
+    profiled_ms = (time.perf_counter() - tp) * 1e3
+    prof_ms, prof_bytes, prof_flops, prof_launches = st.prof_ms, st.prof_bytes, st.prof_flops, st.prof_launches
+    phase_ms = list(st.phase_ms)
+    print(f"[bench] profiled solve: {profiled_ms:.1f} ms, {st.iterations} iterations, {prof_launches} timed "
+          f"applies", file=sys.stderr, flush=True)
 
     # accuracy of the last result, independently of the library (torch FP64 products)
     with torch.no_grad():
@@ -433,7 +455,8 @@ def main():
                     "tflops_frac_fp64": round(prof_flops / (prof_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
 
     cpu = None
-    if args.cpu_iters > 0:
+    cpu_iters = w.get("cpu_iters", 0) if args.cpu_iters < 0 else args.cpu_iters
+    if args.cpu_iters != 0:
         import oracle
         try:
             import threadpoolctl
@@ -441,7 +464,8 @@ def main():
             cores = max([i.get("num_threads", 1) for i in info] or [os.cpu_count()])
         except Exception:
             cores = os.cpu_count()
-        print(f"[bench] CPU oracle sample: {args.cpu_iters} iterations ...", file=sys.stderr, flush=True)
+        what = f"{cpu_iters} iterations" if cpu_iters else "to convergence"
+        print(f"[bench] CPU oracle baseline: {what} ...", file=sys.stderr, flush=True)
         if w["kind"] == "dense" and w.get("metric_dense"):
             # the transformed pencil L^-1 K L^-T, L^-1 M L^-T (B = L L^T) that the library solves
             import scipy.linalg as sla
@@ -462,12 +486,22 @@ def main():
             cop = oracle.CasidaOperator(f.delta, f.L)
         tc = time.perf_counter()
         extra = dict(X0=null, null_on_M=True) if w.get("zeros") else {}
-        r = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U0, U0), maxit=args.cpu_iters, **extra)
+        if cpu_iters:
+            extra["maxit"] = cpu_iters
+        r = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U0, U0), **extra)
         tcpu = time.perf_counter() - tc
-        per_it = tcpu / max(r.iterations, 1)
-        cpu = {"value": round(nev / (per_it * iters), 4), "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
-               "sample": f"oracle BOSP on the same operator and start block, {r.iterations} outer iterations in "
-                         f"{tcpu:.1f}s, scaled to the {iters} iterations the GPU solve needed"}
+        if not r.converged:
+            per_it = tcpu / max(r.iterations, 1)
+            cpu = {"value": round(nev / (per_it * iters), 4), "unit": "eigenpairs/s", "cores": cores,
+                   "kind": "oracle",
+                   "sample": f"oracle BOSP on the same operator and start block: start-up and {r.iterations} "
+                             f"outer iteration(s) in {tcpu:.1f}s, scaled to the {iters} iterations the GPU solve "
+                             f"needed (a solve to convergence would take hours on the host)"}
+        else:
+            cpu = {"value": round(nev / tcpu, 4), "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
+                   "sample": f"oracle BOSP on the same operator and start block, solved to convergence: "
+                             f"{r.iterations} outer iterations (the GPU solve: {iters}) in {tcpu:.1f}s",
+                   "iterations": r.iterations}
 
     lat_s = sorted(lat)
     out = {
@@ -483,7 +517,8 @@ def main():
         "p50_ms": round(lat_s[len(lat_s) // 2], 3), "p99_ms": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 3),
         "iterations": iters, "biorth_restores": restores, "max_residual_Hnorm": max_res, "biorth": biorth,
         "phase_ms_per_solve": dict(zip(["init", "small_problem", "convergence_check", "pq", "wz"],
-                                       [round(v / args.steps, 2) for v in phase_ms])),
+                                       [round(v, 2) for v in phase_ms])),
+        "profiled_solve_ms": round(profiled_ms, 1),
         "roofline": roofline, "cpu_baseline": cpu,
     }
     if metric_setup_ms is not None:

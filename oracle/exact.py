@@ -78,3 +78,22 @@ def casida_count_below(delta, L, lam):
     S = np.eye(L.shape[1]) + W.T @ (W / d2[:, None])
     ev = np.linalg.eigvalsh(0.5 * (S + S.T))
     return int(np.count_nonzero(d2 < 0) - np.count_nonzero(ev < 0))
+
+
+def casida_count_below_many(delta, L, lams, chunk=16384):
+    """casida_count_below for every value in ``lams`` (the same Haynsworth
+    count, with W formed once and the sum W^T (D^2 - mu I)^-1 W taken over
+    row chunks); returns a list of counts in the order of ``lams``."""
+    W = np.sqrt(2.0 * delta)[:, None] * L
+    d2all = delta * delta
+    r = L.shape[1]
+    out = []
+    for lam in lams:
+        mu = float(lam) * float(lam)
+        S = np.eye(r)
+        for s in range(0, W.shape[0], chunk):
+            Wc = W[s:s + chunk]
+            S += Wc.T @ (Wc / (d2all[s:s + chunk] - mu)[:, None])
+        ev = np.linalg.eigvalsh(0.5 * (S + S.T))
+        out.append(int(np.count_nonzero(d2all - mu < 0) - np.count_nonzero(ev < 0)))
+    return out

@@ -102,12 +102,14 @@ def test_config3_casida_full_size(ctx):
     assert res.max() <= 1e-8, res.max()
     assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12
     assert np.all(np.diff(lam) >= 0)
-    # sampled eigenvalues: exactly k - 1 eigenvalues lie below lam_k (1 - 1e-10)
-    # and at least k below lam_k (1 + 1e-10)
-    for kk in (1, 32, 64, 96, 128):
-        lk = lam[kk - 1]
-        assert exact.casida_count_below(dl, Lh, lk * (1 - 1e-10)) <= kk - 1, kk
-        assert exact.casida_count_below(dl, Lh, lk * (1 + 1e-10)) >= kk, kk
+    # every eigenvalue bracketed by the inertia count: at most k - 1 eigenvalues
+    # of H lie below lam_k (1 - 1e-10) and at least k below lam_k (1 + 1e-10),
+    # so each lam_k is within 1e-10 relative of the k-th smallest eigenvalue
+    lo = exact.casida_count_below_many(dl, Lh, lam * (1 - 1e-10))
+    hi = exact.casida_count_below_many(dl, Lh, lam * (1 + 1e-10))
+    bad = [kk for kk in range(1, nev + 1) if not (lo[kk - 1] <= kk - 1 and hi[kk - 1] >= kk)]
+    print(f"[fullsize] casida: {nev - len(bad)} of {nev} eigenvalues bracketed at 1e-10", flush=True)
+    assert not bad, [(kk, lo[kk - 1], hi[kk - 1]) for kk in bad[:10]]
 
 
 def test_config2_full_size_metric(ctx):

@@ -115,6 +115,42 @@ def test_block_mgs_biorth(ctx, n, m, same):
     np.testing.assert_allclose(Q, Qo, atol=1e-9 * np.abs(Qo).max())
 
 
+@pytest.mark.parametrize("row", list(range(5)))
+def test_block_mgs_biorth_ill_conditioned_table(ctx, row):
+    """The inputs of the paper's table of biorthogonality loss (Section 3.1):
+    X = the first m columns of the n x n Hilbert matrix, Y = the first m
+    columns of the Lauchli matrix (mu = 1e-3), m = n / 2, n = 4 ... 20, with
+    zero rows appended up to 64 (inner products unchanged).  The block form
+    (two coefficient passes) must lose no more biorthogonality than the
+    paper's column-by-column MGS-Biorth (its printed ||P^T Q - I||_2) and keep
+    every pair the oracle keeps; at n = 20 the second pass may drop the last
+    pair, whose pivot after the first pass is below the near-orthogonality
+    bar (|eta| <= 1e-10 ||p|| ||q||)."""
+    from conftest import load_golden
+    tab = load_golden("biorth_loss_table.txt")
+    n, mgs_printed = int(tab[row][0]), tab[row][5]
+    m = n // 2
+    X = np.zeros((64, m))
+    Y = np.zeros((64, m))
+    X[:n] = gen.hilbert(n)[:, :m]
+    Y[:n] = gen.lauchli(n, 1e-3)[:, :m]
+    Xd, Yd = dev_colmajor(X, torch).T.contiguous().T, dev_colmajor(Y, torch).T.contiguous().T
+    print(f"[mgs table] n={n} m={m}", flush=True)
+    k = L.lrep_test_block_mgs(ctx, Xd, Yd)
+    P, Q = host(Xd)[:, :k], host(Yd)[:, :k]
+    loss = np.linalg.norm(P.T @ Q - np.eye(k), 2) if k else 0.0
+    Po, Qo, kept = oracle.mgs_biorth(X, Y)
+    oloss = np.linalg.norm(Po.T @ Qo - np.eye(len(kept)), 2)
+    print(f"[mgs table] n={n}: block kept {k}/{m}, loss {loss:.2e}; oracle MGS kept {len(kept)}, loss {oloss:.2e}; "
+          f"printed MGS {mgs_printed:.2e}", flush=True)
+    assert np.all(P[n:] == 0.0) and np.all(Q[n:] == 0.0)
+    assert k == len(kept) or (n == 20 and k == len(kept) - 1), (k, len(kept))
+    assert loss <= mgs_printed, (loss, mgs_printed)
+    # the kept columns still span the inputs (least-squares residual of X in span(P))
+    c = np.linalg.lstsq(P, X, rcond=None)[0]
+    assert np.abs(X - P @ c).max() <= 1e-9 * np.abs(X).max()
+
+
 def test_block_mgs_drops_dependent_columns(ctx):
     rng = np.random.default_rng(11)
     X = rng.standard_normal((500, 6))

@@ -52,7 +52,7 @@ def test_example_4_2_constant_null_vector(ctx):
     printed = load_golden("example_4_2_eigenvalues.txt")[:, 1]
     np.testing.assert_allclose(lam, printed, rtol=1e-10)
     assert h_residual(lambda v: K @ v, lambda v: M @ v, X, Y, lam, 4.0).max() <= 1e-8
-    assert np.abs(X.T @ Y - np.eye(10)).max() <= 1e-10
+    assert np.abs(X.T @ Y - np.eye(10)).max() <= 1e-12
 
 
 @pytest.mark.parametrize("metric", [False, True], ids=["plain", "with_metric"])

@@ -159,8 +159,12 @@ def test_casida_count_against_bruteforce():
     H = np.block([[np.zeros((300, 300)), f.K()], [f.M(), np.zeros((300, 300))]])
     ev = np.sort(np.linalg.eigvals(H).real)
     pos = ev[ev > 0]
-    for lam in [0.2, 0.5, 1.3, 7.0]:
+    lams = [0.2, 0.5, 1.3, 7.0] + list(np.sort(pos)[[0, 5, 40, 120]] * (1 + 1e-9))
+    for lam in lams:
         assert exact.casida_count_below(f.delta, f.L, lam) == int(np.count_nonzero(pos < lam))
+    # the batched form (W formed once, row chunks smaller than n) gives the same counts
+    assert exact.casida_count_below_many(f.delta, f.L, lams, chunk=64) == [
+        int(np.count_nonzero(pos < lam)) for lam in lams]
 
 
 @pytest.mark.slow
