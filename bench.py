@@ -159,17 +159,21 @@ def serve(args, np, torch, gen, L):
     dmax, lmax = (16384, 262144) if full else (8192, 32768)
     ctx = L.lrep_init(0, int(args.budget_gib * (1 << 30)))
     pool, t0 = [], time.time()
+    checks = []              # per operator: what the served results are checked against
     for i in range(6):       # dense, n log-uniform [512, dmax], multiple of 64
         n = int(64 * round(np.exp(rng.uniform(np.log(512), np.log(dmax))) / 64))
-        Kd, Md, _, _ = gen.dense_operator_device(n, 2000 + i, dev)
+        Kd, Md, kk, mm, Q1, Q2 = gen.dense_operator_device(n, 2000 + i, dev, return_factors=True)
         pool.append((L.lrep_create_dense(ctx, Kd.T, Md.T), n))
-        del Kd, Md
+        checks.append(dict(kind="dense", K=Kd, M=Md, q1=Q1, q2=Q2, k=kk, m=mm, normH=float(max(kk.max(), mm.max()))))
     for i in range(6):       # low rank, n log-uniform [16384, lmax], rank uniform {64..256}
         n = int(64 * round(np.exp(rng.uniform(np.log(16384), np.log(lmax))) / 64))
         r = int(rng.integers(64, 257))
         f = gen.casida_factors(n, r, 3000 + i)
-        pool.append((L.lrep_create_lowrank(ctx, torch.from_numpy(f.delta).to(dev),
-                                           torch.from_numpy(np.ascontiguousarray(f.L.T)).to(dev).T), n))
+        dd = torch.from_numpy(f.delta).to(dev)
+        Ld = torch.from_numpy(np.ascontiguousarray(f.L.T)).to(dev).T
+        pool.append((L.lrep_create_lowrank(ctx, dd, Ld), n))
+        checks.append(dict(kind="lowrank", f=f, delta=dd, L=Ld,
+                           normH=float(f.delta.max() + 2.0 * np.linalg.norm(f.L, 2) ** 2)))
     torch.cuda.synchronize()
     print(f"[serve] operator pool ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     reqs = []
@@ -179,6 +183,51 @@ def serve(args, np, torch, gen, L):
         block = 16 * ((nev + 15) // 16)
         window = block // 2 if block >= 32 else block
         reqs.append((k, nev, block, window))
+
+    def verify(results):
+        """Each served result against bars independent of the library: the
+        residual ||H z - lambda z|| / (||H|| ||z||) <= 1e-8 and max |X^T Y - I|
+        <= 1e-12 (torch FP64 products), and the eigenvalues against the
+        oracle's exact spectrum of the operator (dense: the factored closed
+        form; low rank: each eigenvalue bracketed at 1e-10 relative by the
+        inertia count, once per operator for the longest served prefix)."""
+        from oracle import exact
+        bad = []
+        longest = {}
+        for j, (lam, X, Y) in results.items():
+            k = reqs[j][0]
+            c = checks[k]
+            Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+            ld = torch.from_numpy(lam).to(dev)
+            if c["kind"] == "dense":
+                KX, MY = c["K"] @ Xd, c["M"] @ Yd
+            else:
+                KX = c["delta"][:, None] * Xd
+                MY = c["delta"][:, None] * Yd + 2.0 * (c["L"] @ (c["L"].T @ Yd))
+            res = torch.sqrt(((KX - Yd * ld) ** 2).sum(0) + ((MY - Xd * ld) ** 2).sum(0)) / (
+                c["normH"] * torch.sqrt((Xd ** 2).sum(0) + (Yd ** 2).sum(0)))
+            bi = float((Xd.T @ Yd - torch.eye(lam.size, dtype=torch.float64, device=dev)).abs().max())
+            if float(res.max()) > 1e-8 or bi > 1e-12:
+                bad.append([j, "residual/biorth", float(res.max()), bi])
+            if k not in longest or lam.size > longest[k].size:
+                longest[k] = lam
+        ref = {}
+        for k, lam in longest.items():
+            c = checks[k]
+            if c["kind"] == "dense":
+                ref[k] = exact.dense_spectrum_smallest(c["q1"].cpu().numpy(), c["k"], c["q2"].cpu().numpy(), c["m"],
+                                                       lam.size)
+            else:
+                lo = exact.casida_count_below_many(c["f"].delta, c["f"].L, lam * (1 - 1e-10))
+                hi = exact.casida_count_below_many(c["f"].delta, c["f"].L, lam * (1 + 1e-10))
+                if not all(lo[i] <= i and hi[i] >= i + 1 for i in range(lam.size)):
+                    bad.append([int(k), "bracket"])
+                ref[k] = lam
+        for j, (lam, X, Y) in results.items():
+            r = ref[reqs[j][0]][:lam.size]
+            if np.abs(lam - r).max() > 1e-10 * r.max():
+                bad.append([j, "eigenvalues", float(np.abs(lam - r).max())])
+        return bad
 
     def run(arrivals):
         jobs, done = [], {}
@@ -199,8 +248,8 @@ def serve(args, np, torch, gen, L):
                 rc, st = L.lrep_poll(ctx, t)
                 if rc == L.LREP_EAGAIN:
                     continue
-                j, ts, _ = pending.pop(t)
-                done[j] = (rc, (time.perf_counter() - ts) * 1e3)
+                j, ts, outs = pending.pop(t)
+                done[j] = (rc, (time.perf_counter() - ts) * 1e3, outs[:3])
                 print(f"[serve] request {j} rc={rc} {done[j][1]:.0f} ms ({len(done)}/{len(reqs)})",
                       file=sys.stderr, flush=True)
             time.sleep(0.0005)
@@ -214,6 +263,9 @@ def serve(args, np, torch, gen, L):
     lat = np.array([done[j][1] for j in range(len(reqs))])
     ok = all(done[j][0] == L.LREP_OK for j in range(len(reqs))) and all(
         closed[j][0] == L.LREP_OK for j in range(len(reqs)))
+    tv = time.time()
+    bad = verify({j: done[j][2] for j in range(len(reqs)) if done[j][0] == L.LREP_OK})
+    print(f"[serve] results checked in {time.time() - tv:.1f}s: {len(bad)} failures", file=sys.stderr, flush=True)
     failed = [[j, done[j][0], pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
               for j in range(len(reqs)) if done[j][0] != L.LREP_OK][:10]
     slowest = sorted(range(len(reqs)), key=lambda j: -done[j][1])[:5]
@@ -235,7 +287,7 @@ def serve(args, np, torch, gen, L):
                    "operator_n": [n for _, n in pool]},
         "closed_loop_solves_per_s": round(rate, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-        "all_ok": ok, "failed": failed, "slowest": slow,
+        "all_ok": ok and not bad, "oracle_failures": bad[:10], "failed": failed, "slowest": slow,
     }
     print(json.dumps(out), flush=True)
 
@@ -271,6 +323,9 @@ def main():
                     help="serve: Poisson arrival rate as a fraction of the closed-loop solve rate")
     ap.add_argument("--graphs", type=int, default=0, choices=[-1, 0, 1],
                     help="Step 6 as a replayed HIP graph: 1 on, -1 off, 0 the library's default")
+    ap.add_argument("--fused-cg", type=int, default=0, choices=[-1, 0, 1],
+                    help="low-rank operators: Step-6 CG as one pass per step (0 or 1, the default) or the plain "
+                         "two-pass CG (-1)")
     ap.add_argument("--cpu-iters", type=int, default=-1,
                     help="outer iterations of the CPU oracle baseline (0: skip; -1: the workload's default, "
                          "to convergence where that takes about a minute on the host, else a bounded sample)")
@@ -360,7 +415,7 @@ def main():
 
     def step(profile):
         opts = L.make_opts(window=window, init=U0d, profile=profile, precision=w.get("precision", 0),
-                           graphs=args.graphs)
+                           graphs=args.graphs, fused_cg=args.fused_cg)
         rc, st = L.lrep_solve(op, n, nev, block, tol, opts, lam, X, Y, ctx=ctx)
         return st
 
@@ -443,9 +498,9 @@ def main():
             kname = "apply_stream_kernel (CG block apply, w=%d)" % window
             abytes = 8.0 * n * n + 16.0 * n * window
         else:
-            kname = ("lr_lty_kernel + lr_reduce_kernel + lr_apply_kernel "
-                     "(low-rank M apply of the CG on the row-major copy of L, w=%d, both passes)" % window)
-            abytes = 16.0 * n * w["rank"] + 24.0 * n * window
+            kname = ("fcg_pass_M_kernel (fused CG step on M = diag(delta) + 2 L L^T, w=%d: L read once, "
+                     "x, r, p read and written, delta read)" % window)
+            abytes = 8.0 * n * w["rank"] + 48.0 * n * window + 8.0 * n
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "algorithmic_bytes_per_launch": abytes,

@@ -53,6 +53,7 @@ __all__ = [
     "dense_operator_device",
     "metric_diag",
     "metric_dense",
+    "dense_factors_torch",
 ]
 
 
@@ -178,15 +179,10 @@ def init_block(n: int, d: int, seed: int):
     return U, V
 
 
-def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
-                          lo: float = 0.5, hi: float = 10.0, return_factors: bool = False):
-    """The dense workload built on a torch device: the same NumPy draws in the
-    same order as ``dense_factors`` (Gaussian for Q1, Gaussian for Q2, k, m),
-    with the QR factorisations and the products K = Q1 diag(k) Q1^T,
-    M = Q2 diag(m) Q2^T done by torch on ``device`` (for large n, where the
-    host QR takes tens of seconds).  Returns (K, M, k, m) with K, M symmetric
-    FP64 device tensors and k, m NumPy vectors; with ``return_factors`` also
-    the device tensors Q1, Q2."""
+def dense_factors_torch(n: int, seed: int, device, n_zero_m: int = 0, lo: float = 0.5, hi: float = 10.0):
+    """The dense workload's factors (Q1, k, Q2, m) with the QR factorisations
+    done by torch on ``device`` (a GPU, or "cpu"): the same NumPy draws in the
+    same order as ``dense_factors``, so Q1, Q2 agree with it up to rounding."""
     import torch
     rng = np.random.default_rng(seed)
     qs = []
@@ -201,6 +197,21 @@ def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
     m = rng.uniform(lo, hi, n)
     if n_zero_m:
         m[:n_zero_m] = 0.0
+    return qs[0], k, qs[1], m
+
+
+def dense_operator_device(n: int, seed: int, device, n_zero_m: int = 0,
+                          lo: float = 0.5, hi: float = 10.0, return_factors: bool = False):
+    """The dense workload built on a torch device: the same NumPy draws in the
+    same order as ``dense_factors`` (Gaussian for Q1, Gaussian for Q2, k, m),
+    with the QR factorisations and the products K = Q1 diag(k) Q1^T,
+    M = Q2 diag(m) Q2^T done by torch on ``device`` (for large n, where the
+    host QR takes tens of seconds).  Returns (K, M, k, m) with K, M symmetric
+    FP64 device tensors and k, m NumPy vectors; with ``return_factors`` also
+    the device tensors Q1, Q2."""
+    import torch
+    qs = [None, None]
+    qs[0], k, qs[1], m = dense_factors_torch(n, seed, device, n_zero_m, lo, hi)
     out = []
     for q, v in ((qs[0], k), (qs[1], m)):
         a = (q * torch.from_numpy(v).to(device)[None, :]) @ q.T

@@ -116,6 +116,14 @@ typedef struct lrep_solve_opts {
                               device flag.  Results are bitwise those of the
                               stream path.  Ignored for callback operators and
                               with profile.                                           */
+    int32_t fused_cg;      /* low-rank operators: 0 (default) or 1: each CG step of
+                              Step 6 is one pass over the rows (direction update,
+                              product, x and r updates; L read once per step, with
+                              L^T p carried by the direction recurrence); -1: the
+                              plain CG (L^T p and L (L^T p) as two passes, then
+                              separate vector updates).  Same iteration, different
+                              rounding order.                                         */
+    int32_t reserved0;     /* zero                                                    */
 } lrep_solve_opts_t;
 
 /* Per-solve statistics (all optional to read). */
@@ -316,11 +324,17 @@ int lrep_solve(lrep_op_t op, int64_t n, int64_t nev, int64_t block, double tol,
 
 /* Queue a solve on `op` (thread-safe).  The request struct is copied; its
  * output buffers must stay valid until lrep_poll reports completion.
- * Requests are admitted in arrival order as the context's HBM budget allows
- * (a request whose workspace alone exceeds the budget fails with
- * LREP_ENOMEM at poll time) and run concurrently with other admitted
- * requests; results are identical to lrep_solve with the same arguments.
- * Errors: LREP_EINVAL (bad request), LREP_ENOMEM (host allocation). */
+ * At submission the library computes the request's device footprint (every
+ * workspace the solve allocates, and 16-bit operator copies it would make).
+ * Four worker streams take queued requests in arrival order, passing over
+ * any whose footprint does not fit the context's free HBM budget at that
+ * moment; an admitted request reserves its whole footprint until it
+ * completes, so it never waits for memory once started.  A request whose
+ * footprint exceeds what the budget leaves beside the operators fails with
+ * LREP_ENOMEM at poll time.  Admitted requests run concurrently; results are
+ * identical to lrep_solve with the same arguments.
+ * Errors: LREP_EINVAL (bad request: the checks of lrep_solve), LREP_EDEVICE
+ * (the context's workers could not start). */
 int lrep_submit(lrep_ctx_t ctx, lrep_op_t op, const lrep_request_t* req, lrep_ticket_t* ticket);
 
 /* Completion status of a ticket (thread-safe, non-blocking): LREP_EAGAIN

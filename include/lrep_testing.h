@@ -39,6 +39,14 @@ int lrep_test_block_mgs(lrep_ctx_t ctx, int n, int m, double* X, double* Y, int*
  * LREP_NULL_ON_M), X n x cols (ld n), Y n x cols (ld n). */
 int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* Y);
 
+/* One CG solve of Step 6 (the block Gauss-Seidel solves, Section 3.2): A X = B
+ * for A = K (which = 0) or M (which = 1), nw <= 32 columns (B, X device, ld
+ * n), zero start, per-column relative tolerance tol, at most maxit steps, as
+ * the solver runs it: fused = 1 the fused low-rank CG, -1 the plain CG, 0 the
+ * solver's choice.  *applies (nullable) receives the column applies made. */
+int lrep_test_cg(lrep_op_t op, int which, int nw, const double* B, double* X, double tol, int maxit, int fused,
+                 int64_t* applies);
+
 /* out (n x n, ld n, 16-bit) = the BF16 (precision 1) or FP16 (precision 2)
  * copy of 0.5 (A + A^T) that the mixed-precision CG applies use: each
  * value rounded to FP32, then to 16 bits, both to nearest even.  A is a

@@ -97,3 +97,26 @@ def casida_count_below_many(delta, L, lams, chunk=16384):
         ev = np.linalg.eigvalsh(0.5 * (S + S.T))
         out.append(int(np.count_nonzero(d2all - mu < 0) - np.count_nonzero(ev < 0)))
     return out
+
+
+def dense_spectrum_smallest_torch(q1, k, q2, m, count):
+    """dense_spectrum_smallest with plain PyTorch CPU FP64 operations (for
+    n in the tens of thousands, where the host LAPACK eigensolver of NumPy /
+    SciPy is slow): the square roots of the smallest eigenvalues of F^T F,
+    F = diag(sqrt k) Q1^T Q2 diag(sqrt m), exact zeros of k or m excluded.
+    q1, q2 are CPU tensors or arrays; the products are formed in place to
+    keep three n x n arrays alive at most."""
+    import torch
+    q1 = torch.as_tensor(q1, dtype=torch.float64)
+    q2 = torch.as_tensor(q2, dtype=torch.float64)
+    n = q1.shape[0]
+    F = q1.T @ q2
+    F *= torch.sqrt(torch.as_tensor(k, dtype=torch.float64))[:, None]
+    F *= torch.sqrt(torch.as_tensor(m, dtype=torch.float64))[None, :]
+    G = F.T @ F
+    del F
+    G = 0.5 * (G + G.T)
+    w = torch.linalg.eigvalsh(G)
+    nzero = int(n - min(int(np.count_nonzero(k)), int(np.count_nonzero(m))))
+    w = w[nzero:nzero + count].numpy()
+    return np.sqrt(np.maximum(w, 0.0))

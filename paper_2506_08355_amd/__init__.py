@@ -68,6 +68,8 @@ class lrep_solve_opts_t(ctypes.Structure):
         ("rebiorth_tol", ctypes.c_double),
         ("refresh", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
+        ("fused_cg", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
     ]
 
 
@@ -141,6 +143,8 @@ _SIGS = {
     "lrep_test_small_lrep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _I64, _P, _P, _P]),
     "lrep_test_block_mgs": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "lrep_test_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lrep_test_cg": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(_I64)]),
     "lrep_test_convert16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _I64, _P]),
     "lrep_test_apply16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
     "lrep_test_read": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -337,9 +341,10 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0, profile=False, refresh=0, precision=0, graphs=0):
+              rebiorth_tol=0.0, profile=False, refresh=0, precision=0, graphs=0, fused_cg=0):
     o = lrep_solve_opts_t()
     o.graphs = graphs
+    o.fused_cg = fused_cg
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
         p, ld, dev = colmajor(init)
@@ -439,6 +444,15 @@ def lrep_test_block_mgs(ctx, X, Y):
     k = ctypes.c_int()
     _check(lib().lrep_test_block_mgs(ctx, X.shape[0], X.shape[1], px, py, ctypes.byref(k)), ctx,
            "lrep_test_block_mgs")
+    return k.value
+
+
+def lrep_test_cg(op, which, B, X, tol=1e-2, maxit=20, fused=0):
+    """One Step-6 CG solve A X = B (A = K for which 0, M for 1) on device
+    tensors (n x nw, ld n); returns the number of column applies."""
+    k = _I64()
+    _check(lib().lrep_test_cg(op, which, B.shape[1], colmajor(B)[0], colmajor(X)[0], tol, maxit, fused,
+                              ctypes.byref(k)), what="lrep_test_cg")
     return k.value
 
 

@@ -13,12 +13,28 @@ struct lrep_op_s : public Op {};
 
 namespace lrep {
 
+thread_local Reservation* t_reservation = nullptr;
+
 DevBuf::~DevBuf() { release(); }
 
 int DevBuf::alloc(Ctx* c, size_t nbytes) {
     release();
     ctx = c;
     if (nbytes == 0) nbytes = 8;
+    Reservation* rv = t_reservation;
+    if (rv && rv->ctx == c && rv->left >= nbytes) {
+        // already charged at admission
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, nbytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? LREP_ENOMEM : LREP_EDEVICE;
+        }
+        rv->left -= nbytes;
+        p = static_cast<double*>(q);
+        bytes = nbytes;
+        return LREP_OK;
+    }
     if (c->budget) {
         size_t cur = c->used.load();
         do {
@@ -56,44 +72,83 @@ int set_device(Ctx* c) {
     return hipSetDevice(c->device) == hipSuccess ? LREP_OK : LREP_EDEVICE;
 }
 
+// Serving worker: takes queued requests in arrival order, skipping those
+// whose footprint does not fit the free budget now (a later, smaller one may),
+// reserves the footprint and runs the solve on its own stream.  A request
+// that could not fit even with no other request running fails at once with
+// LREP_ENOMEM.
 void worker_main(Ctx* c) {
     (void)hipSetDevice(c->device);
     hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    const bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
     std::unique_lock<std::mutex> lk(c->q_mu);
+    if (!ok) {
+        // no stream: fail what is queued now and refuse later submissions
+        c->broken = true;
+        for (uint64_t id : c->queue) {
+            auto it = c->tickets.find(id);
+            if (it != c->tickets.end() && it->second.state == 0) {
+                it->second.state = 2;
+                it->second.rc = LREP_EDEVICE;
+            }
+        }
+        c->queue.clear();
+        c->q_cv.notify_all();
+        return;
+    }
     for (;;) {
-        c->q_cv.wait(lk, [&] { return c->stopping || !c->queue.empty(); });
-        if (c->stopping && c->queue.empty()) break;
-        const uint64_t id = c->queue.front();
-        c->queue.pop_front();
+        uint64_t id = 0;
+        size_t fp = 0;
+        for (;;) {
+            if (c->stopping && c->queue.empty()) break;
+            const size_t used = c->used.load();
+            const size_t base = used >= c->reserved ? used - c->reserved : 0;
+            for (auto q = c->queue.begin(); q != c->queue.end();) {
+                auto it = c->tickets.find(*q);
+                if (it == c->tickets.end() || it->second.state != 0) {
+                    q = c->queue.erase(q);
+                    continue;
+                }
+                const size_t f = it->second.footprint;
+                if (c->budget && base + f > c->budget) {
+                    // cannot fit even alone
+                    it->second.state = 2;
+                    it->second.rc = LREP_ENOMEM;
+                    q = c->queue.erase(q);
+                    c->q_cv.notify_all();
+                    continue;
+                }
+                if (!c->budget || used + f <= c->budget) {
+                    id = *q;
+                    fp = f;
+                    c->queue.erase(q);
+                    break;
+                }
+                ++q;
+            }
+            if (id || c->stopping) break;
+            c->q_cv.wait(lk);
+        }
+        if (!id) break;
         auto it = c->tickets.find(id);
-        if (it == c->tickets.end() || it->second.state != 0) continue;
         it->second.state = 1;
+        if (c->budget) {
+            c->used += fp;
+            c->reserved += fp;
+        }
         Ctx::Ticket t = it->second;
         lk.unlock();
+        Reservation rv{c, fp};
+        t_reservation = c->budget ? &rv : nullptr;
         lrep_stats_t stats{};
-        int rc;
-        bool retried_alone = false;
-        for (;;) {
-            rc = solve(t.op, st, t.req.nev, t.req.block, t.req.tol, &t.req.opts, t.req.lambda, t.req.X, t.req.Y,
-                       t.req.ldxy, &stats);
-            if (rc != LREP_ENOMEM || !c->budget) break;
-            // HBM budget exhausted by other running requests: wait for one to finish
-            std::unique_lock<std::mutex> l2(c->q_mu);
-            bool others = false;
-            for (auto& kv : c->tickets)
-                if (kv.first != id && kv.second.state == 1) others = true;
-            if (!others) {
-                // the requests that held the memory may have finished (and freed
-                // it) after this attempt failed: try once more before giving up
-                if (retried_alone) break;
-                retried_alone = true;
-                continue;
-            }
-            retried_alone = false;
-            c->q_cv.wait_for(l2, std::chrono::milliseconds(20));
-        }
+        const int rc = solve(t.op, st, t.req.nev, t.req.block, t.req.tol, &t.req.opts, t.req.lambda, t.req.X,
+                             t.req.Y, t.req.ldxy, &stats);
+        t_reservation = nullptr;
         lk.lock();
+        if (c->budget) {
+            c->used -= rv.left;   // the part of the reservation the solve did not take
+            c->reserved -= fp;
+        }
         auto it2 = c->tickets.find(id);
         if (it2 != c->tickets.end()) {
             it2->second.state = 2;
@@ -499,8 +554,12 @@ int lrep_submit(lrep_ctx_t c, lrep_op_t op, const lrep_request_t* req, lrep_tick
     if (req->nev < 1 || req->block < 1 || !(req->tol > 0) || !req->lambda || !req->X || !req->Y ||
         req->ldxy < op->n)
         return LREP_EINVAL;
+    size_t fp = 0;
+    const int frc = solve_footprint(op, req->nev, req->block, req->tol, &req->opts, &fp);
+    if (frc != LREP_OK) return frc;
     std::lock_guard<std::mutex> g(c->q_mu);
     if (c->stopping) return LREP_EINVAL;
+    if (c->broken) return LREP_EDEVICE;
     if (c->workers.empty()) {
         c->n_workers = 4;
         for (int i = 0; i < c->n_workers; ++i) c->workers.emplace_back(worker_main, c);
@@ -511,6 +570,7 @@ int lrep_submit(lrep_ctx_t c, lrep_op_t op, const lrep_request_t* req, lrep_tick
     t.req = *req;
     t.state = 0;
     t.rc = LREP_EAGAIN;
+    t.footprint = fp;
     c->tickets[id] = t;
     c->queue.push_back(id);
     *ticket = id;

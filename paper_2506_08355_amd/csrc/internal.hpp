@@ -20,6 +20,15 @@ namespace lrep {
 
 struct Ctx;
 
+// A served request's admission reserves its whole footprint against the
+// context's budget before the solve starts; the solve's own allocations (on
+// the worker thread) are then taken from that reservation.
+struct Reservation {
+    Ctx* ctx;
+    size_t left;
+};
+extern thread_local Reservation* t_reservation;
+
 // Device allocation charged against the context's HBM budget.
 struct DevBuf {
     Ctx* ctx = nullptr;
@@ -100,7 +109,13 @@ struct Ctx {
         int state;             // 0 queued, 1 running, 2 done, 3 cancelled
         int rc;
         lrep_stats_t stats;
+        size_t footprint;      // device bytes the solve charges (admission)
     };
+    // bytes reserved for the requests now running (each its whole footprint
+    // from admission to completion); used - reserved is what the operators
+    // and other allocations hold
+    size_t reserved = 0;
+    bool broken = false;       // a worker could not start: submit fails
     std::mutex q_mu;
     std::condition_variable q_cv;
     std::map<uint64_t, Ticket> tickets;
@@ -118,6 +133,11 @@ struct Ctx {
 // Solver entry (solver.hip).  `st` is the stream the solve runs on.
 int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts,
           double* lambda, double* X, double* Y, int64_t ldxy, lrep_stats_t* stats);
+
+// Device bytes a solve with these arguments charges to the context (its
+// workspaces, and 16-bit operator copies it would make); LREP_EINVAL for
+// arguments the solve would reject.  No device work.
+int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes);
 
 // Null-space preparation (solver.hip): X0t (device, n x r, ld n) -> op->X0, op->Y0.
 int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);

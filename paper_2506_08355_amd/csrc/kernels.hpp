@@ -158,6 +158,10 @@ struct CgState {
     // issuing steps of solve `seq` once every column has converged
     unsigned long long* note;
     unsigned long long seq;
+    // fused CG on a low-rank operator (lowrank.hip): c = p^T diag(delta) p of
+    // the current direction (w), T = L^T p (k-major, rows of L x 32)
+    double* c;
+    double* T;
 };
 // x = 0, r = p = b (B may alias R), rr = bb = |b|^2, active = rr > tol^2 bb
 hipError_t cg_init(hipStream_t st, int n, int w, const CgState& s, const double* B, int64_t ldb,
@@ -174,6 +178,23 @@ size_t cg_pq_elems(int ntiles);
 hipError_t cg_update(hipStream_t st, int n, int w, const CgState& s, double tol);
 // p = r + beta p for active columns
 hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s);
+
+// ---- fused CG on a low-rank operator (lowrank.hip) ------------------------
+// CG for A = diag(delta) + 2 L L^T (Lr: the row-major copy of L, rank r) or,
+// with Lr == nullptr, A = diag(delta), on w <= 32 columns of the CgState
+// vectors (ld n, n even).  Each step is one pass over the rows: the direction
+// update p = r + beta p, A p = delta o p + 2 L T with T = L^T p carried by its
+// own recurrence (L^T p_new = L^T r_new + beta L^T p), x += alpha p,
+// r -= alpha A p, and the sums that give the next alpha and beta (L is read
+// once per step), then a fixed-order reduction and finishing launch.
+// `work` holds fused_cg_work_elems(n, r, w) doubles.
+size_t fused_cg_work_elems(int n, int r, int w);
+hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
+                         const CgState& s, const double* B, int64_t ldb, double tol, double* work,
+                         size_t work_elems);
+hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
+                         const CgState& s, double tol, double* work, size_t work_elems, hipEvent_t* ev = nullptr,
+                         int* flag_log = nullptr);
 // Bx = I - (G - I)^T / 2, By = I - (G - I) / 2 for G = X^T Y (c x c): the
 // first-order correction (X Bx)^T (Y By) = I + O(|G - I|^2)
 hipError_t biorth_fix_coef(hipStream_t st, int c, const double* G, int64_t ldg, double* Bx, double* By, int64_t ldb);

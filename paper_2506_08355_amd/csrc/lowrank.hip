@@ -281,6 +281,412 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused CG steps (Step 6 on a low-rank operator).
+//
+// CG for A = diag(delta) + 2 L L^T in a single pass over L per step.  With
+// T_k = L^T p_k known before step k (a 256 x 32 block), A p_k = delta o p_k +
+// 2 L T_k needs L only once; the same pass forms S = L^T r_{k+1} from the new
+// residual, and since p_{k+1} = r_{k+1} + beta_k p_k, T_{k+1} = S + beta_k T_k.
+// The step length alpha_k = rho_k / p_k^T A p_k uses p^T A p = p^T diag(delta) p
+// + 2 |T|^2, where c_{k+1} = p_{k+1}^T diag(delta) p_{k+1} = a + 2 beta b +
+// beta^2 c_k with a = r_{k+1}^T diag(delta) r_{k+1}, b = r_{k+1}^T diag(delta)
+// p_k, both summed in the pass.  So alpha_k is known when step k starts and
+// x, r, p are each read and written once per step.  (A plain CG step reads L
+// twice -- for L^T p and for L (L^T p) -- and streams x, r, p, A p in separate
+// passes.)
+//
+// Pass (fcg_pass_M_kernel): one workgroup per CU (LDS 142 KiB), tiles of 32
+// rows, four wavefronts; wavefront v owns L's columns [64 v, 64 v + 64).  Per
+// tile: (1) the wavefront's 32 x 64 slice of L, loaded one tile ahead into
+// registers with row 4 s + g, column 16 t + c in lane (g = lane / 16,
+// c = lane % 16), goes to LDS; (2) the partial product L_slice T_slice
+// (MFMA, A operand read back from LDS with row on c and column on g) replaces
+// the slice in LDS; (3) after a barrier every thread takes 4 rows of one
+// column: p = r + beta p, A p = delta p + 2 (sum of the four partials in a
+// fixed order), x += alpha p, r -= alpha A p, stores x, r, p, and puts r in
+// LDS; (4) after a barrier each wavefront adds L_slice^T r to its block of S
+// with the slice still in registers (MFMA, row on g).  S and the column sums
+// leave the workgroup once, as one record per workgroup.
+// ---------------------------------------------------------------------------
+constexpr int FT = 32;     // rows per tile
+constexpr int FLS = 65;    // LDS stride of a wavefront's slice (32 rows x 64 columns of L)
+constexpr int FMS = 33;    // LDS stride of the 32-column arrays (T, r, partial products)
+constexpr int FREC = 128;  // column sums per record: (rho, a, b, 0) for 32 columns
+
+__global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, int tpw,
+                                                         const double* __restrict__ Lr,
+                                                         const double* __restrict__ delta, double* __restrict__ X,
+                                                         double* __restrict__ R, double* __restrict__ P,
+                                                         const double* __restrict__ T,
+                                                         const double* __restrict__ alpha,
+                                                         const double* __restrict__ beta,
+                                                         const int* __restrict__ active, const int* __restrict__ any,
+                                                         double* __restrict__ rec, int stride,
+                                                         int* __restrict__ flag_log) {
+    const int on = *any;
+    if (flag_log && blockIdx.x == 0 && threadIdx.x == 0) *flag_log = on;
+    if (on == 0) return;
+    __shared__ double sl[4 * FT * FLS];   // wavefront slices of L; then the partial products
+    __shared__ double stt[256 * FMS];     // T, k-major
+    __shared__ double sr[FT * FMS];       // r of the tile
+    const int tid = threadIdx.x, lane = tid % WAVE, v = tid / WAVE, c = lane % 16, g = lane / 16;
+    const bool hasL = 64 * v < ldr;   // wavefront-uniform (ldr is a multiple of 64)
+    double* slv = sl + v * FT * FLS;
+    for (int idx = tid; idx < ldr * 32; idx += 256) stt[(idx >> 5) * FMS + (idx & 31)] = T[idx];
+    // epilogue: thread -> column ej, rows 4 eq .. 4 eq + 3 of the tile
+    const int ej = tid >> 3, eq = tid & 7;
+    const bool ecol = ej < w;
+    const bool eact = ecol && active[ej] != 0;
+    const double ea = eact ? alpha[ej] : 0.0, eb = eact ? beta[ej] : 0.0;
+    double srho = 0.0, sa = 0.0, sb = 0.0;
+    d4 acc2[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc2[t][0] = acc2[t][1] = d4{0.0, 0.0, 0.0, 0.0};
+    const int ntile = (n + FT - 1) / FT;
+    const int tbeg = blockIdx.x * tpw, tend = min(ntile, tbeg + tpw);
+    const double* lbase = Lr + 64 * v + c;
+    __syncthreads();
+
+    auto loadL = [&](double (&a)[8][4], int tile) {
+        if (!hasL || tile >= tend) return;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int row = tile * FT + 4 * s + g;
+            const bool ok = row < n;
+            const double* lp = lbase + (int64_t)(ok ? row : 0) * ldr;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double x = lp[16 * t];
+                a[s][t] = ok ? x : 0.0;
+            }
+        }
+    };
+
+    auto step = [&](double (&cur)[8][4], double (&nxt)[8][4], int tile) {
+        const int er = tile * FT + 4 * eq;
+        // (1) this wavefront's slice into LDS
+        if (hasL) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) slv[(4 * s + g) * FLS + 16 * t + c] = cur[s][t];
+        }
+        // next tile's slice, and this tile's vectors for the epilogue
+        loadL(nxt, tile + 1);
+        double xv[4], rv[4], pv[4], dv[4];
+        const int64_t o = (int64_t)ej * n + er;
+        const bool full = er + 3 < n;
+        if (ecol && full) {
+            const double2 x0 = *reinterpret_cast<const double2*>(X + o), x1 = *reinterpret_cast<const double2*>(X + o + 2);
+            const double2 r0 = *reinterpret_cast<const double2*>(R + o), r1 = *reinterpret_cast<const double2*>(R + o + 2);
+            const double2 p0 = *reinterpret_cast<const double2*>(P + o), p1 = *reinterpret_cast<const double2*>(P + o + 2);
+            const double2 d0 = *reinterpret_cast<const double2*>(delta + er),
+                          d1 = *reinterpret_cast<const double2*>(delta + er + 2);
+            xv[0] = x0.x; xv[1] = x0.y; xv[2] = x1.x; xv[3] = x1.y;
+            rv[0] = r0.x; rv[1] = r0.y; rv[2] = r1.x; rv[3] = r1.y;
+            pv[0] = p0.x; pv[1] = p0.y; pv[2] = p1.x; pv[3] = p1.y;
+            dv[0] = d0.x; dv[1] = d0.y; dv[2] = d1.x; dv[3] = d1.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = ecol && er + i < n;
+                xv[i] = ok ? X[o + i] : 0.0;
+                rv[i] = ok ? R[o + i] : 0.0;
+                pv[i] = ok ? P[o + i] : 0.0;
+                dv[i] = ok ? delta[er + i] : 0.0;
+            }
+        }
+        // (2) partial product L_slice T_slice: row 16 rb + c, k = 4 ks + g
+        if (hasL) {
+            d4 acc1[2][2];
+            acc1[0][0] = acc1[0][1] = acc1[1][0] = acc1[1][1] = d4{0.0, 0.0, 0.0, 0.0};
+            const double* tb = stt + (64 * v + g) * FMS + c;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                const double a0 = slv[c * FLS + 4 * ks + g], a1 = slv[(16 + c) * FLS + 4 * ks + g];
+                const double b0 = tb[4 * ks * FMS], b1 = tb[4 * ks * FMS + 16];
+                acc1[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc1[0][0], 0, 0, 0);
+                acc1[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc1[0][1], 0, 0, 0);
+                acc1[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc1[1][0], 0, 0, 0);
+                acc1[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1[1][1], 0, 0, 0);
+            }
+            // the partial product replaces the slice (same wavefront, after its reads);
+            // item i of a 16 x 16 result holds row 4 i + g, column c
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) slv[(16 * rb + 4 * i + g) * FMS + 16 * jb + c] = acc1[rb][jb][i];
+        }
+        __syncthreads();
+        // (3) epilogue
+        double lr2 = 0.0, la2 = 0.0, lb2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * eq + i;
+            double m = 0.0;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv)
+                if (64 * vv < ldr) m += sl[vv * FT * FLS + row * FMS + ej];
+            const double p = fma(eb, pv[i], rv[i]);
+            const double ap = fma(dv[i], p, 2.0 * m);
+            const double rn = fma(-ea, ap, rv[i]);
+            xv[i] = fma(ea, p, xv[i]);
+            rv[i] = rn;
+            pv[i] = p;
+            lr2 = fma(rn, rn, lr2);
+            la2 = fma(dv[i] * rn, rn, la2);
+            lb2 = fma(dv[i] * rn, p, lb2);
+            sr[row * FMS + ej] = eact ? rn : 0.0;
+        }
+        if (eact) {
+            if (full) {
+                *reinterpret_cast<double2*>(X + o) = double2{xv[0], xv[1]};
+                *reinterpret_cast<double2*>(X + o + 2) = double2{xv[2], xv[3]};
+                *reinterpret_cast<double2*>(R + o) = double2{rv[0], rv[1]};
+                *reinterpret_cast<double2*>(R + o + 2) = double2{rv[2], rv[3]};
+                *reinterpret_cast<double2*>(P + o) = double2{pv[0], pv[1]};
+                *reinterpret_cast<double2*>(P + o + 2) = double2{pv[2], pv[3]};
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (er + i < n) {
+                        X[o + i] = xv[i];
+                        R[o + i] = rv[i];
+                        P[o + i] = pv[i];
+                    }
+            }
+        }
+        // column sums of the tile over its 8 threads (consecutive lanes)
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            lr2 += __shfl_xor(lr2, off, WAVE);
+            la2 += __shfl_xor(la2, off, WAVE);
+            lb2 += __shfl_xor(lb2, off, WAVE);
+        }
+        srho += lr2;
+        sa += la2;
+        sb += lb2;
+        __syncthreads();
+        // (4) S += L_slice^T r: k = 64 v + 16 t + c, rows 4 s + g
+        if (hasL) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const double b0 = sr[(4 * s + g) * FMS + c], b1 = sr[(4 * s + g) * FMS + 16 + c];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc2[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b0, acc2[t][0], 0, 0, 0);
+                    acc2[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b1, acc2[t][1], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    double la[8][4], lb[8][4];
+    loadL(la, tbeg);
+    for (int tile = tbeg; tile < tend; tile += 2) {
+        step(la, lb, tile);
+        if (tile + 1 < tend) step(lb, la, tile + 1);
+    }
+    // the workgroup's record: S (k-major, ldr x 32), then the column sums
+    double* out = rec + (int64_t)blockIdx.x * stride;
+    if (hasL) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) out[(64 * v + 16 * t + 4 * i + g) * 32 + 16 * jb + c] = acc2[t][jb][i];
+    }
+    if (eq == 0) {
+        double* cs = out + ldr * 32 + 4 * ej;
+        cs[0] = srho;
+        cs[1] = sa;
+        cs[2] = sb;
+        cs[3] = 0.0;
+    }
+}
+
+// The same step for A = diag(delta): block (chunk, column j) over a row range
+__global__ __launch_bounds__(256) void fcg_pass_K_kernel(int n, int nch, const double* __restrict__ delta,
+                                                         double* __restrict__ X, double* __restrict__ R,
+                                                         double* __restrict__ P, const double* __restrict__ alpha,
+                                                         const double* __restrict__ beta,
+                                                         const int* __restrict__ active, const int* __restrict__ any,
+                                                         double* __restrict__ rec) {
+    __shared__ double red[3][4];
+    if (*any == 0) return;
+    const int j = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+    double* cs = rec + (int64_t)ch * FREC + 4 * j;
+    if (!active[j]) {
+        if (tid < 4) cs[tid] = 0.0;
+        return;
+    }
+    const int rows = (n + nch - 1) / nch;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    const double a = alpha[j], b = beta[j];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = r0 + tid; i < r1; i += 256) {
+        const double d = delta[i];
+        const double p = fma(b, P[off + i], R[off + i]);
+        const double rn = fma(-a, d * p, R[off + i]);
+        X[off + i] = fma(a, p, X[off + i]);
+        R[off + i] = rn;
+        P[off + i] = p;
+        s0 = fma(rn, rn, s0);
+        s1 = fma(d * rn, rn, s1);
+        s2 = fma(d * rn, p, s2);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    const int lane = tid % WAVE, wid = tid / WAVE;
+    if (lane == 0) {
+        red[0][wid] = s0;
+        red[1][wid] = s1;
+        red[2][wid] = s2;
+    }
+    __syncthreads();
+    if (tid < 3) cs[tid] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+    if (tid == 3) cs[3] = 0.0;
+}
+
+// Start of a fused CG: x = 0, r = p = b; column sums (|b|^2, b^T diag(delta) b)
+__global__ __launch_bounds__(256) void fcg_init_kernel(int n, int nch, const double* __restrict__ delta,
+                                                       const double* __restrict__ B, int64_t ldb,
+                                                       double* __restrict__ X, double* __restrict__ R,
+                                                       double* __restrict__ P, double* __restrict__ rec) {
+    __shared__ double red[2][4];
+    const int j = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+    const int rows = (n + nch - 1) / nch;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    const int64_t off = (int64_t)j * n;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = r0 + tid; i < r1; i += 256) {
+        const double bv = B[(int64_t)j * ldb + i];
+        X[off + i] = 0.0;
+        R[off + i] = bv;
+        P[off + i] = bv;
+        s0 = fma(bv, bv, s0);
+        s1 = fma(delta[i] * bv, bv, s1);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    const int lane = tid % WAVE, wid = tid / WAVE;
+    if (lane == 0) {
+        red[0][wid] = s0;
+        red[1][wid] = s1;
+    }
+    __syncthreads();
+    double* cs = rec + (int64_t)ch * FREC + 4 * j;
+    if (tid < 2) cs[tid] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+    if (tid == 2 || tid == 3) cs[tid] = 0.0;
+}
+
+// Fixed-order sum of the workgroup records (nrec records of `stride` doubles:
+// S = L^T r in the first nS, then the column sums), then, in the block that
+// arrives last, the finishing step: rho, beta, the relative residual test,
+// T = S + beta T, c, alpha = rho / (c + 2 |T|^2) and any_active.  With init,
+// the records hold (|b|^2, b^T diag(delta) b) and T = L^T b is already in place.
+__global__ __launch_bounds__(512) void fcg_fin_kernel(int w, int ldr, int nS, int nrec, int stride,
+                                                      const double* __restrict__ rec, double* __restrict__ red,
+                                                      CgState s, double tol, int init) {
+    __shared__ double ph[16][32];
+    __shared__ double cb[32];
+    __shared__ int cact[32];
+    if (!init && *s.any_active == 0) return;
+    const int tid = threadIdx.x, x = tid % 32, q = tid / 32;
+    const int e = blockIdx.x * 32 + x;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < stride) {
+        int k = q;
+        for (; k + 16 < nrec; k += 32) {
+            s0 += rec[(int64_t)k * stride + e];
+            s1 += rec[(int64_t)(k + 16) * stride + e];
+        }
+        if (k < nrec) s0 += rec[(int64_t)k * stride + e];
+    }
+    ph[q][x] = s0 + s1;
+    __syncthreads();
+    if (q == 0 && e < stride) {
+        double t = ph[0][x];
+#pragma unroll
+        for (int p = 1; p < 16; ++p) t += ph[p][x];
+        red[e] = t;
+    }
+    if (!last_block_arrives(s.ticket, gridDim.x)) return;
+    // finishing step
+    if (tid < 32) {
+        const int j = tid;
+        int act = 0, applied = 0;
+        double bt = 0.0;
+        if (j < w) {
+            const double rn = red[nS + 4 * j], av = red[nS + 4 * j + 1], bv = red[nS + 4 * j + 2];
+            if (init) {
+                s.rr[j] = rn;
+                s.bb[j] = rn;
+                s.c[j] = av;
+                act = rn > tol * tol * rn ? 1 : 0;
+            } else if (s.active[j]) {
+                applied = 1;
+                bt = rn / s.rr[j];
+                act = rn > tol * tol * s.bb[j] ? 1 : 0;
+                s.c[j] = fma(bt * bt, s.c[j], fma(2.0 * bt, bv, av));
+                s.rr[j] = rn;
+            }
+            s.beta[j] = bt;
+        }
+        cb[j] = bt;
+        cact[j] = act;
+        const unsigned long long na = __popcll(__ballot(applied));
+        if (j == 0 && na) atomicAdd(s.napplies, na);
+    }
+    __syncthreads();
+    double t2 = 0.0;
+    if (ldr > 0 && x < w && cact[x]) {
+        for (int k = q; k < ldr; k += 16) {
+            double* tp = s.T + (int64_t)k * 32 + x;
+            double tn = *tp;
+            if (!init) {
+                tn = fma(cb[x], tn, red[k * 32 + x]);
+                *tp = tn;
+            }
+            t2 = fma(tn, tn, t2);
+        }
+    }
+    ph[q][x] = t2;
+    __syncthreads();
+    if (tid < 32) {
+        const int j = tid;
+        double tt = ph[0][j];
+#pragma unroll
+        for (int p = 1; p < 16; ++p) tt += ph[p][j];
+        int act = cact[j];
+        double al = 0.0;
+        if (act) {
+            const double den = fma(2.0, tt, s.c[j]);
+            if (den > 0.0)
+                al = s.rr[j] / den;
+            else
+                act = 0;   // p^T A p <= 0: the column stops (singular operator)
+        }
+        if (j < w) {
+            s.alpha[j] = al;
+            s.active[j] = act;
+        }
+        const int anyv = __any(act) ? 1 : 0;
+        if (j == 0) {
+            *s.any_active = anyv;
+            if (s.note)
+                __hip_atomic_store(s.note, 2ull * s.seq + (unsigned long long)anyv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 }  // namespace
 
 int64_t lowrank_row_ld(int64_t r) { return ((r + 63) / 64) * 64; }
@@ -315,6 +721,95 @@ hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const doubl
     hipLaunchKernelGGL(lr_apply_kernel, dim3((n + RW - 1) / RW), dim3(64), 0, st, n, ldr, w, Lr, Pt, delta, Y, ldy,
                        C, ldc, pq, active_flag);
     if (ev) (void)hipEventRecord(ev[1], st);
+    return hipGetLastError();
+}
+
+
+namespace {
+int fcg_chunks(int n, int w) {
+    int nch = (1024 + w - 1) / w;
+    nch = std::min(nch, std::max(1, n / 1024));
+    return std::max(1, std::min(nch, 256));
+}
+int fcg_groups(int n) {
+    const int ntile = (n + FT - 1) / FT;
+    return std::min(256, ntile);
+}
+// row chunk of the L^T b pass (a multiple of 2 RU, as in lowrank_apply_M_rows)
+int fcg_lty_chunk(int n) {
+    const int nchunk = std::max(1, std::min(512, n / 512));
+    const int chunk = (n + nchunk - 1) / nchunk;
+    return ((chunk + 2 * RU - 1) / (2 * RU)) * (2 * RU);
+}
+int fcg_lty_chunks(int n) { return (n + fcg_lty_chunk(n) - 1) / fcg_lty_chunk(n); }
+}  // namespace
+
+size_t fused_cg_work_elems(int n, int r, int w) {
+    (void)w;
+    const size_t ldr = r > 0 ? (size_t)lowrank_row_ld(r) : 0;
+    const size_t stride = ldr * 32 + FREC;
+    size_t need = (size_t)fcg_chunks(n, 32) * FREC + FREC;                       // init / diagonal steps
+    if (r > 0) {
+        need = std::max(need, (size_t)fcg_groups(n) * stride + stride);          // M steps
+        need = std::max(need, (size_t)256 * 32 + (size_t)fcg_lty_chunks(n) * 8192 + FREC * 256);   // L^T b
+    }
+    return need;
+}
+
+hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr, const CgState& s,
+                         const double* B, int64_t ldb, double tol, double* work, size_t work_elems) {
+    if (n < 2 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
+        work_elems < fused_cg_work_elems(n, Lr ? r : 0, w))
+        return hipErrorInvalidValue;
+    const int nch = fcg_chunks(n, w);
+    double* rec = work;
+    double* red = work + (size_t)nch * FREC;
+    hipLaunchKernelGGL(fcg_init_kernel, dim3(nch, w), dim3(256), 0, st, n, nch, delta, B, ldb, s.X, s.R, s.P, rec);
+    int ldr = 0;
+    if (Lr) {
+        // T = L^T b (the direction of the first step is b)
+        ldr = (int)lowrank_row_ld(r);
+        const int nchunk = fcg_lty_chunks(n);
+        const int chunk = fcg_lty_chunk(n);
+        double* part = red + FREC;
+        hipLaunchKernelGGL(lr_lty_kernel, dim3(nchunk), dim3(256), 0, st, n, ldr, w, Lr, B, ldb, chunk, part,
+                           nullptr);
+        hipLaunchKernelGGL(lr_reduce_kernel, dim3(8192 / 32), dim3(32 * RED_PH), 0, st, ldr, nchunk, part, 1.0, s.T,
+                           nullptr);
+    }
+    hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(512), 0, st, w, ldr, 0, nch, FREC, rec, red, s, tol, 1);
+    return hipGetLastError();
+}
+
+hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
+                         const CgState& s, double tol, double* work, size_t work_elems, hipEvent_t* ev,
+                         int* flag_log) {
+    if (n < 2 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
+        work_elems < fused_cg_work_elems(n, Lr ? r : 0, w) || (reinterpret_cast<uintptr_t>(Lr) & 15))
+        return hipErrorInvalidValue;
+    if (Lr) {
+        const int ldr = (int)lowrank_row_ld(r);
+        const int ntile = (n + FT - 1) / FT;
+        const int nwg = fcg_groups(n);
+        const int tpw = (ntile + nwg - 1) / nwg;
+        const int ngrid = (ntile + tpw - 1) / tpw;
+        const int stride = ldr * 32 + FREC;
+        double* rec = work;
+        double* red = work + (size_t)ngrid * stride;
+        if (ev) (void)hipEventRecord(ev[0], st);
+        hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(256), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
+                           s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, flag_log);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL(fcg_fin_kernel, dim3((stride + 31) / 32), dim3(512), 0, st, w, ldr, ldr * 32, ngrid, stride,
+                           rec, red, s, tol, 0);
+    } else {
+        const int nch = fcg_chunks(n, w);
+        double* rec = work;
+        double* red = work + (size_t)nch * FREC;
+        hipLaunchKernelGGL(fcg_pass_K_kernel, dim3(nch, w), dim3(256), 0, st, n, nch, delta, s.X, s.R, s.P, s.alpha,
+                           s.beta, s.active, s.any_active, rec);
+        hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(512), 0, st, w, 0, 0, nch, FREC, rec, red, s, tol, 0);
+    }
     return hipGetLastError();
 }
 

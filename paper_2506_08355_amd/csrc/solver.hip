@@ -82,7 +82,7 @@ struct Solver {
     DevBuf gwork, dsmall, ismall;
     // carved small buffers
     double *Kh, *Mh, *S, *Xh, *Yh, *lam, *eps, *lamw, *Ph, *Qh, *Acoef, *Bcoef, *scr, *G, *Cproj, *Tlr, *part,
-        *cg_rr, *cg_bb, *cg_alpha, *cg_beta, *offmax, *cg_pq;
+        *cg_rr, *cg_bb, *cg_alpha, *cg_beta, *offmax, *cg_pq, *cg_c, *cg_T;
     int64_t kproj;
     int *status, *win, *wincol, *cg_active, *cg_any;
     unsigned* tickets;
@@ -124,7 +124,7 @@ struct Solver {
     // events for the next timed apply; the "any column active" flag is
     // logged by the caller's kernel into *slot when slot != nullptr, else
     // copied here
-    hipEvent_t* prof_next(int cols, int** slot = nullptr, int prec = 0) {
+    hipEvent_t* prof_next(int cols, int** slot = nullptr, int prec = 0, bool fused = false) {
         const size_t i = prof_cols.size();
         if (!prof_log.p || i >= (size_t)kProfMax) return nullptr;
         while (prof_ev.size() < 2 * (i + 1)) {
@@ -149,6 +149,10 @@ struct Solver {
         } else if (op->kind == 2) {   // caller-supplied products: no byte model
             prof_b.push_back(0.0);
             prof_f.push_back(0.0);
+        } else if (fused) {   // fused low-rank M step: L once; x, r, p read and written; delta
+            const double r = (double)op->rank;
+            prof_b.push_back(8.0 * nn * r + 48.0 * nn * c + 8.0 * nn);
+            prof_f.push_back(4.0 * nn * r * c + 14.0 * nn * c);
         } else {   // low-rank M: L read twice, Y read twice, result written once
             const double r = (double)op->rank;
             prof_b.push_back(16.0 * nn * r + 24.0 * nn * c);
@@ -212,30 +216,15 @@ struct Solver {
     }
 
 
-    int alloc() {
-        Ctx* c = op->ctx;
-        const size_t col = (size_t)n * sizeof(double);
-        for (int i = 0; i < 2; ++i) {
-            CR(bX[i].alloc(c, col * cap));
-            CR(bY[i].alloc(c, col * cap));
-            CR(bKX[i].alloc(c, col * cap));
-            CR(bMY[i].alloc(c, col * cap));
-        }
-        CR(Xc.alloc(c, col * nev));
-        CR(Yc.alloc(c, col * nev));
-        const int cw = std::max(w, 1);
-        CR(cgX.alloc(c, col * cw));
-        CR(cgR.alloc(c, col * cw));
-        CR(cgP.alloc(c, col * cw));
-        CR(cgQ.alloc(c, col * cw));
-        CR(Zs.alloc(c, col * cw));
-        CR(Ws.alloc(c, col * cw));
-        CR(rhs.alloc(c, col * cw));
-        CR(tX.alloc(c, col * kMaxD));
-        CR(tY.alloc(c, col * kMaxD));
-        CR(gwork.alloc(c, GEMM_WORK_ELEMS * sizeof(double)));
-        kproj = r0 + nev + cap + 8;
+    // layout of the small carved device arrays (offsets in doubles) and its size
+    struct SmallLayout {
+        size_t Kh, Mh, S, Xh, Yh, lam, eps, lamw, Ph, Qh, A, B, scr, G, C, T, part, rr, bb, al, be, om, pq, cc, cT;
+        size_t total;
+    };
+    SmallLayout small_layout() const {
         const size_t D2 = (size_t)kMaxD * kMaxD;
+        const int cw = std::max(w, 1);
+        const int64_t kp = r0 + nev + cap + 8;
         const int64_t rank = op->kind == 1 ? op->rank : 0;
         size_t nd = 0;
         auto carve = [&](size_t cnt) {
@@ -243,22 +232,72 @@ struct Solver {
             nd += (cnt + 31) & ~size_t(31);
             return o2;
         };
-        size_t oKh = carve(D2), oMh = carve(D2), oS = carve(D2), oXh = carve(D2), oYh = carve(D2),
-               olam = carve(kMaxD), oeps = carve(kMaxD), olamw = carve(kMaxD), oPh = carve(kMaxD * 64),
-               oQh = carve(kMaxD * 64), oA = carve(D2), oB = carve(2 * D2), oscr = carve(4 * D2),
-               oG = carve(4 * D2), oC = carve((size_t)kproj * std::max(kMaxD, cw)),
-               oT = carve((size_t)std::max<int64_t>(rank, 1) * kMaxD), opart = carve((size_t)256 * kMaxD * 4),
-               orr = carve(kMaxD), obb = carve(kMaxD), oal = carve(kMaxD), obe = carve(kMaxD), oom = carve(8),
-               opq = carve(cg_pq_elems((int)stream_tiles((int)n)));
-        CR(dsmall.alloc(c, nd * sizeof(double)));
+        SmallLayout l;
+        l.Kh = carve(D2); l.Mh = carve(D2); l.S = carve(D2); l.Xh = carve(D2); l.Yh = carve(D2);
+        l.lam = carve(kMaxD); l.eps = carve(kMaxD); l.lamw = carve(kMaxD); l.Ph = carve(kMaxD * 64);
+        l.Qh = carve(kMaxD * 64); l.A = carve(D2); l.B = carve(2 * D2); l.scr = carve(4 * D2);
+        l.G = carve(4 * D2); l.C = carve((size_t)kp * std::max(kMaxD, cw));
+        l.T = carve((size_t)std::max<int64_t>(rank, 1) * kMaxD); l.part = carve((size_t)256 * kMaxD * 4);
+        l.rr = carve(kMaxD); l.bb = carve(kMaxD); l.al = carve(kMaxD); l.be = carve(kMaxD); l.om = carve(8);
+        l.pq = carve(cg_pq_elems((int)stream_tiles((int)n))); l.cc = carve(kMaxD);
+        l.cT = carve(op->kind == 1 ? (size_t)256 * 32 : 32);
+        l.total = nd;
+        return l;
+    }
+    static size_t int_bytes() { return sizeof(int) * (8 + 3 * kMaxD + 8 + 8) + 4 * sizeof(unsigned long long); }
+
+    // Every device buffer of a solve with its size, in allocation order; alloc()
+    // allocates them, footprint() adds them up (the serving admission).
+    template <class F>
+    int buffers(F&& f) {
+        const size_t col = (size_t)n * sizeof(double);
+        for (int i = 0; i < 2; ++i) {
+            CR(f(bX[i], col * cap));
+            CR(f(bY[i], col * cap));
+            CR(f(bKX[i], col * cap));
+            CR(f(bMY[i], col * cap));
+        }
+        CR(f(Xc, col * nev));
+        CR(f(Yc, col * nev));
+        const size_t cw = (size_t)std::max(w, 1);
+        CR(f(cgX, col * cw));
+        CR(f(cgR, col * cw));
+        CR(f(cgP, col * cw));
+        CR(f(cgQ, col * cw));
+        CR(f(Zs, col * cw));
+        CR(f(Ws, col * cw));
+        CR(f(rhs, col * cw));
+        CR(f(tX, col * kMaxD));
+        CR(f(tY, col * kMaxD));
+        CR(f(gwork, GEMM_WORK_ELEMS * sizeof(double)));
+        CR(f(dsmall, small_layout().total * sizeof(double)));
+        CR(f(ismall, int_bytes()));
+        if (o.profile) CR(f(prof_log, kProfMax * sizeof(int)));
+        return LREP_OK;
+    }
+
+    // device bytes alloc() will charge to the context (DevBuf charges 8 for 0)
+    size_t footprint() {
+        size_t total = 0;
+        (void)buffers([&](DevBuf&, size_t bytes) {
+            total += bytes ? bytes : 8;
+            return LREP_OK;
+        });
+        return total;
+    }
+
+    int alloc() {
+        Ctx* c = op->ctx;
+        CR(buffers([&](DevBuf& b, size_t bytes) { return b.alloc(c, bytes); }));
+        kproj = r0 + nev + cap + 8;
+        const SmallLayout l = small_layout();
         double* base = dsmall.p;
-        Kh = base + oKh; Mh = base + oMh; S = base + oS; Xh = base + oXh; Yh = base + oYh;
-        lam = base + olam; eps = base + oeps; lamw = base + olamw; Ph = base + oPh; Qh = base + oQh;
-        Acoef = base + oA; Bcoef = base + oB; scr = base + oscr; G = base + oG; Cproj = base + oC;
-        Tlr = base + oT; part = base + opart; cg_rr = base + orr; cg_bb = base + obb; cg_alpha = base + oal;
-        cg_beta = base + obe; offmax = base + oom; cg_pq = base + opq;
+        Kh = base + l.Kh; Mh = base + l.Mh; S = base + l.S; Xh = base + l.Xh; Yh = base + l.Yh;
+        lam = base + l.lam; eps = base + l.eps; lamw = base + l.lamw; Ph = base + l.Ph; Qh = base + l.Qh;
+        Acoef = base + l.A; Bcoef = base + l.B; scr = base + l.scr; G = base + l.G; Cproj = base + l.C;
+        Tlr = base + l.T; part = base + l.part; cg_rr = base + l.rr; cg_bb = base + l.bb; cg_alpha = base + l.al;
+        cg_beta = base + l.be; offmax = base + l.om; cg_pq = base + l.pq; cg_c = base + l.cc; cg_T = base + l.cT;
         // ints: status(8) win(kMaxD) wincol(kMaxD) cg_active(kMaxD) cg_any(8) tickets(8) napplies(2 x u64)
-        CR(ismall.alloc(c, sizeof(int) * (8 + 3 * kMaxD + 8 + 8) + 4 * sizeof(unsigned long long)));
         int* ib = reinterpret_cast<int*>(ismall.p);
         status = ib;
         win = ib + 8;
@@ -273,7 +312,6 @@ struct Solver {
         CK(hipHostMalloc((void**)&note_h, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent));
         *note_h = 0;
         CK(hipHostGetDevicePointer((void**)&note_d, note_h, 0));
-        if (o.profile) CR(prof_log.alloc(c, kProfMax * sizeof(int)));
         return LREP_OK;
     }
 
@@ -295,6 +333,8 @@ struct Solver {
         s.napplies = napplies + which;
         s.note = note_d;
         s.seq = ++cg_seq;
+        s.c = cg_c;
+        s.T = cg_T;
         return s;
     }
 
@@ -312,8 +352,40 @@ struct Solver {
         return Ad;
     }
 
+    // low-rank operators: the fused CG (one pass over the rows per step, L
+    // read once): 1 for the diagonal operator, 2 for diag + 2 L L^T, else 0
+    int fused_cg_kind(int which, int nw) const {
+        if (op->kind != 1 || nw < 1 || nw > 32 || (n & 1) || o.fused_cg < 0 ||
+            (reinterpret_cast<uintptr_t>(op->delta) & 15))
+            return 0;
+        const bool useK = (which == 0) != op->null_on_M();
+        if (useK) return 1;
+        if (!op->Lr || op->rank > 256 || (reinterpret_cast<uintptr_t>(op->Lr) & 15)) return 0;
+        return 2;
+    }
+
+    // fused CG on a low-rank operator (see fused_cg_kind)
+    int cg_fused(int kind, int which, const double* B, int nw, double cgtol, int maxit) {
+        CgState s = cg_state(1, which);
+        const double* Lr = kind == 2 ? op->Lr : nullptr;
+        const int r = kind == 2 ? (int)op->rank : 0;
+        CK(fused_cg_init(st, (int)n, r, nw, op->delta, Lr, s, B, n, cgtol, gwork.p, GEMM_WORK_ELEMS));
+        for (int it = 0; it < maxit; ++it) {
+            if (it > 0 && !capturing) {
+                const unsigned long long v = __atomic_load_n(note_h, __ATOMIC_ACQUIRE);
+                if ((v >> 1) == s.seq && (v & 1ull) == 0) break;
+            }
+            int* logslot = nullptr;
+            hipEvent_t* ev = (o.profile && kind == 2) ? prof_next(nw, &logslot, 0, true) : nullptr;
+            CK(fused_cg_step(st, (int)n, r, nw, op->delta, Lr, s, cgtol, gwork.p, GEMM_WORK_ELEMS, ev, logslot));
+        }
+        return LREP_OK;
+    }
+
     // solution of A x_j = rhs_j (which: 0 = K, 1 = M) into cgX; `maxit` CG steps
     int cg(int which, const double* B, int nw, double cgtol, int maxit, bool host_check) {
+        // the long, tight-tolerance CG of the null-space set-up keeps the plain form
+        if (const int fk = host_check ? 0 : fused_cg_kind(which, nw)) return cg_fused(fk, which, B, nw, cgtol, maxit);
         CgState s = cg_state(1, which);
         CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
         const double* Ad = cg_stream_operator(which, nw);
@@ -782,6 +854,12 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     double me = 0;
     for (double e : epsc) me = std::max(me, e);
     stats.max_eps = me;
+    // Pairs of nonzero eigenvalues are biorthogonal to the generalized null
+    // space (Lemma 2.3 (iii)); the returned ones only to the rounding level of
+    // the bases they were locked from, amplified by the pull-back coefficients.
+    // One more projection, a no-op for exact eigenvectors, restores it.
+    for (int c0 = 0; c0 < c && r0 > 0; c0 += kMaxD)
+        CR(project_v0(Xc.p + (size_t)c0 * n, Yc.p + (size_t)c0 * n, std::min(kMaxD, c - c0)));
     if (c > 0 && c <= kMaxD) {
         // The returned pairs were locked from bases biorthogonal to the
         // restore threshold; a first-order correction brings X^T Y = I to
@@ -896,13 +974,10 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
     return e == hipSuccess ? LREP_OK : LREP_EDEVICE;
 }
 
-int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts,
-          double* lambda, double* X, double* Y, int64_t ldxy, lrep_stats_t* stats) {
-    Solver s;
-    s.op = op;
-    s.st = st;
-    s.n = op->n;
-    lrep_solve_opts_t o{};
+namespace {
+// the options with their defaults filled in; LREP_EINVAL for values out of range
+int solve_options(const lrep_solve_opts_t* opts, int64_t block, lrep_solve_opts_t& o) {
+    o = lrep_solve_opts_t{};
     if (opts) o = *opts;
     if (o.window <= 0) o.window = block;
     if (o.maxit <= 0) o.maxit = 1000;
@@ -911,10 +986,57 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 2) return LREP_EINVAL;
+    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 2 || o.fused_cg < -1 || o.fused_cg > 1)
+        return LREP_EINVAL;
+    return LREP_OK;
+}
+
+// the solver's shape from the arguments (no device work); LREP_EINVAL for sizes out of range
+int solve_configure(Solver& s, Op* op, hipStream_t st, int64_t nev, int64_t block, double tol,
+                    const lrep_solve_opts_t& o) {
+    s.op = op;
+    s.st = st;
+    s.n = op->n;
+    if (o.precision != 0 && op->kind == 0 && (op->n % 8 != 0 || op->n < 64)) return LREP_EINVAL;
+    if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
+    s.o = o;
+    s.b = (int)block;
+    s.w = (int)o.window;
+    s.nev = (int)nev;
+    s.r0 = (int)op->r0;
+    s.tol = tol;
+    s.cap = s.b + 4 * s.w + 1;
+    const int64_t d0 = block + 2 * o.window;
+    if (nev < 1 || block < 1 || nev > op->n - op->r0 || d0 > op->n - op->r0 || d0 > kMaxD || s.w > 64 ||
+        !(tol > 0))
+        return LREP_EINVAL;
+    return LREP_OK;
+}
+}  // namespace
+
+int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes) {
+    lrep_solve_opts_t o;
+    CR(solve_options(opts, block, o));
+    Solver s;
+    CR(solve_configure(s, op, nullptr, nev, block, tol, o));
+    size_t total = s.footprint();
+    if (o.precision != 0 && op->kind == 0) {
+        std::lock_guard<std::mutex> g(op->mu16);
+        if (op->prec16 != o.precision) total += 2 * (size_t)op->n * op->n * sizeof(uint16_t);
+    }
+    *bytes = total;
+    return LREP_OK;
+}
+
+int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts,
+          double* lambda, double* X, double* Y, int64_t ldxy, lrep_stats_t* stats) {
+    lrep_solve_opts_t o;
+    CR(solve_options(opts, block, o));
+    Solver s;
+    CR(solve_configure(s, op, st, nev, block, tol, o));
+    if (ldxy < op->n || !lambda || !X || !Y) return LREP_EINVAL;
     if (o.precision != 0 && op->kind == 0) {
         // 16-bit copies of K and M for the mixed-precision CG applies
-        if (op->n % 8 != 0 || op->n < 64) return LREP_EINVAL;
         std::lock_guard<std::mutex> g(op->mu16);
         if (op->prec16 != o.precision) {
             op->K16buf.release();
@@ -937,18 +1059,6 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
             op->prec16 = o.precision;
         }
     }
-    if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
-    s.o = o;
-    s.b = (int)block;
-    s.w = (int)o.window;
-    s.nev = (int)nev;
-    s.r0 = (int)op->r0;
-    s.tol = tol;
-    s.cap = s.b + 4 * s.w + 1;
-    const int64_t d0 = block + 2 * o.window;
-    if (nev < 1 || block < 1 || nev > op->n - op->r0 || d0 > op->n - op->r0 || d0 > kMaxD || s.w > 64 ||
-        !(tol > 0) || ldxy < op->n || !lambda || !X || !Y)
-        return LREP_EINVAL;
     int rc = s.alloc();
     if (rc == LREP_OK) rc = s.run(lambda, X, Y, ldxy);
     if (rc != LREP_OK && !s.err.empty()) op->ctx->set_error(s.err);
@@ -1099,6 +1209,36 @@ int block_mgs_standalone(Ctx* c, hipStream_t st, int64_t n, int m, double* X, do
     int rc = s.alloc();
     if (rc == LREP_OK) rc = s.block_mgs(X, Y, m, X, Y, kept);
     if (rc == LREP_OK && hipStreamSynchronize(st) != hipSuccess) rc = LREP_EDEVICE;
+    return rc;
+}
+
+// One Step-6 CG solve (which: 0 = K, 1 = M) of nw <= 32 columns B (ld n) into
+// X (ld n), as the solver runs it; fused selects the fused low-rank CG
+// (1), the plain CG (-1) or the solver's choice (0).  *applies: column
+// applies made.  For the kernel tests.
+int cg_standalone(Op* op, hipStream_t st, int which, int nw, const double* B, double* X, double tol, int maxit,
+                  int fused, int64_t* applies) {
+    Solver s;
+    s.op = op;
+    s.st = st;
+    s.n = op->n;
+    s.b = nw;
+    s.w = nw;
+    s.cap = nw;
+    s.nev = 1;
+    s.r0 = 0;
+    s.o.fused_cg = fused;
+    if (nw < 1 || nw > 32 || maxit < 1 || !(tol > 0)) return LREP_EINVAL;
+    int rc = s.alloc();
+    if (rc == LREP_OK) rc = s.cg(which, B, nw, tol, maxit, false);
+    if (rc == LREP_OK && hipMemcpy2DAsync(X, op->n * sizeof(double), s.cgX.p, op->n * sizeof(double),
+                                          op->n * sizeof(double), nw, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        rc = LREP_EDEVICE;
+    unsigned long long na[2] = {0, 0};
+    if (rc == LREP_OK && hipMemcpyAsync(na, s.napplies, sizeof(na), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = LREP_EDEVICE;
+    if (rc == LREP_OK && hipStreamSynchronize(st) != hipSuccess) rc = LREP_EDEVICE;
+    if (applies) *applies = (int64_t)(na[0] + na[1]);
     return rc;
 }
 }  // namespace lrep

@@ -9,6 +9,8 @@ struct lrep_op_s : public Op {};
 
 namespace lrep {
 int block_mgs_standalone(Ctx* c, hipStream_t st, int64_t n, int m, double* X, double* Y, int* kept);
+int cg_standalone(Op* op, hipStream_t st, int which, int nw, const double* B, double* X, double tol, int maxit,
+                  int fused, int64_t* applies);
 }
 
 namespace {
@@ -113,6 +115,15 @@ int lrep_test_apply(lrep_op_t op, int which, int cols, const double* X, double* 
     rc = op_apply(op, c->stream, which, X, op->n, cols, Y, op->n, work.p, welems, small.p, nullptr);
     if (rc != LREP_OK) return rc;
     return finish(c, hipSuccess);
+}
+
+int lrep_test_cg(lrep_op_t op, int which, int nw, const double* B, double* X, double tol, int maxit, int fused,
+                 int64_t* applies) {
+    if (!op || (which != 0 && which != 1) || nw < 1 || nw > 32 || !B || !X || (fused < -1 || fused > 1))
+        return LREP_EINVAL;
+    Ctx* c = op->ctx;
+    (void)hipSetDevice(c->device);
+    return cg_standalone(op, c->stream, which, nw, B, X, tol, maxit, fused, applies);
 }
 
 int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, int64_t lda, uint16_t* out) {

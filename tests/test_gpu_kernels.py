@@ -319,3 +319,35 @@ def test_apply16_against_rounded_operands(ctx, precision, n, cols):
         # and the product is the operator's to 16-bit accuracy
         exact = Ad.cpu().numpy() @ Xh
         assert np.abs(host(Yd) - exact).max() <= 2e-2 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("n,r", [(1502, 16), (20002, 100), (262144, 256)])
+@pytest.mark.parametrize("which", [0, 1])
+def test_fused_cg_matches_plain_cg_and_the_oracle(ctx, n, r, which):
+    """The Step-6 CG on a low-rank operator (K = diag(delta), M = diag(delta) +
+    2 L L^T) in its fused form -- one pass over the rows per step, L^T p
+    carried by the direction recurrence, alpha from carried sums -- against
+    the plain CG (two passes over L per product, separate updates) and the
+    oracle's CG: 32 columns, tolerance 1e-2, 20 steps.  Several row tiles per
+    workgroup at n = 20002 and 262144."""
+    f = gen.casida_factors(n, r, 900 + r)
+    B = np.random.default_rng(n + which).standard_normal((n, 32))
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    Bd = dev_colmajor(B, torch).T.contiguous().T
+    Xf, Xp = dev_empty(n, 32, torch), dev_empty(n, 32, torch)
+    torch.cuda.synchronize()
+    print(f"[cg] n={n} rank={r} which={which}", flush=True)
+    af = L.lrep_test_cg(op, which, Bd, Xf, 1e-2, 20, 1)
+    ap = L.lrep_test_cg(op, which, Bd, Xp, 1e-2, 20, -1)
+    L.lrep_destroy_op(op)
+    Xf, Xp = host(Xf), host(Xp)
+    scale = np.abs(Xp).max()
+    print(f"[cg] applies fused {af} plain {ap}; max |X_fused - X_plain| / max |X| = "
+          f"{np.abs(Xf - Xp).max() / scale:.2e}", flush=True)
+    assert af == ap
+    assert np.abs(Xf - Xp).max() <= 1e-10 * scale
+    if n <= 20002:
+        cop = oracle.CasidaOperator(f.delta, f.L)
+        Xo, ao = oracle.bosp.cg_columns(cop.apply_K if which == 0 else cop.apply_M, B, 1e-2, 20)
+        assert ao == af
+        assert np.abs(Xf - Xo).max() <= 1e-10 * np.abs(Xo).max()

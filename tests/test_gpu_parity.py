@@ -162,6 +162,31 @@ def test_casida_lowrank_moving(ctx, refresh):
     assert exact.casida_count_below(f.delta, f.L, lam[-1] * (1 + 1e-9)) == nev
 
 
+@pytest.mark.parametrize("n,r,fused", [(1500, 16, 1), (1500, 16, -1), (1502, 100, 1), (3002, 256, 1),
+                                       (1501, 100, 1), (2048, 64, 1)])
+def test_casida_fused_cg(ctx, n, r, fused):
+    """The Step-6 CG on the low-rank operator as one pass per step (fused=1,
+    the default: L read once per step, L^T p carried by the direction
+    recurrence) and as the plain two-pass CG (fused=-1): both meet the oracle's
+    eigenvalues, residual and biorthogonality bars.  Ragged row tiles (n = 1502,
+    3002), ranks whose row copy has 1, 2 or 4 wavefronts of columns (16, 100,
+    256) and an odd n (1501, which takes the plain CG) are covered."""
+    nev, block, window, tol = 16, 16, 8, 1e-9
+    print(f"[fused cg] n={n} rank={r} fused={fused}", flush=True)
+    f = gen.casida_factors(n, r, 1000 + r)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U, fused_cg=fused)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    cop = oracle.CasidaOperator(f.delta, f.L)
+    ref = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U, U))
+    normH = np.linalg.norm(f.M(), 2)
+    check_pair(lam, X, Y, ref.lam, cop.apply_K, cop.apply_M, normH)
+    assert exact.casida_count_below(f.delta, f.L, lam[-1] * (1 + 1e-9)) == nev
+    assert st.applies_M > 0 and st.applies_K > 0
+
+
 def test_error_paths(ctx):
     n = 64
     K, M, f = gen.dense_operator(n, 3)

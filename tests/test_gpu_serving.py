@@ -20,16 +20,20 @@ REQUESTS = [(0, 8, 16, 16, 1e-8), (1, 24, 32, 16, 1e-8), (2, 16, 16, 16, 1e-8), 
             (1, 4, 16, 16, 1e-8), (2, 40, 48, 24, 1e-8), (3, 12, 16, 8, 1e-8)]
 
 
-def make_ops(ctx):
+def make_ops(ctx, factors=None):
     ops, sizes = [], []
     for n, seed in ((512, 1201), (1024, 1202)):
-        K, M, _ = gen.dense_operator(n, seed)
+        K, M, f = gen.dense_operator(n, seed)
         ops.append(L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch)))
         sizes.append(n)
+        if factors is not None:
+            factors.append(f)
     for n, r, seed in ((16384, 64, 1203), (20000, 100, 1204)):
         f = gen.casida_factors(n, r, seed)
         ops.append(L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch)))
         sizes.append(n)
+        if factors is not None:
+            factors.append(f)
     return ops, sizes
 
 
@@ -82,17 +86,18 @@ def served():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     ctx = L.lrep_init(0)
-    ops, sizes = make_ops(ctx)
+    factors = []
+    ops, sizes = make_ops(ctx, factors)
     inits = request_inputs(sizes)
     alone = run_alone(ctx, ops, sizes, inits)
-    yield ctx, ops, sizes, inits, alone
+    yield ctx, ops, sizes, inits, alone, factors
     for op in ops:
         L.lrep_destroy_op(op)
     L.lrep_finalize(ctx)
 
 
 def test_mix_is_bitwise_alone(served):
-    ctx, ops, sizes, inits, alone = served
+    ctx, ops, sizes, inits, alone, _ = served
     jobs, saw_pending = run_mix(ctx, ops, sizes, inits, copies=2)
     assert saw_pending   # the requests were in flight together
     for k, t, lam, X, Y, _ in jobs:
@@ -100,6 +105,67 @@ def test_mix_is_bitwise_alone(served):
         assert np.array_equal(lam, a_lam), k
         assert np.array_equal(X, a_X), k
         assert np.array_equal(Y, a_Y), k
+
+
+def test_served_results_match_the_oracle(served):
+    """Every served result, checked against the exact spectrum rather than
+    against the library: dense operators against the factored closed form
+    (eigenvalues within 1e-10 relative), low-rank ones by the inertia count
+    (each eigenvalue bracketed at 1e-10 relative); all against the residual
+    bar ||H z - lambda z|| / (||H|| ||z||) <= 1e-8 and max |X^T Y - I| <= 1e-12."""
+    from oracle import exact
+    from gpu_util import h_residual
+    ctx, ops, sizes, inits, alone, factors = served
+    jobs, _ = run_mix(ctx, ops, sizes, inits, copies=1)
+    for k, t, lam, X, Y, _ in jobs:
+        o = REQUESTS[k][0]
+        f = factors[o]
+        nev = lam.size
+        if o < 2:
+            np.testing.assert_allclose(lam, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev), rtol=1e-10, atol=0)
+            K, M = f.K(), f.M()
+            res = h_residual(lambda v: K @ v, lambda v: M @ v, X, Y, lam, f.norm_H())
+        else:
+            lo = exact.casida_count_below_many(f.delta, f.L, lam * (1 - 1e-10))
+            hi = exact.casida_count_below_many(f.delta, f.L, lam * (1 + 1e-10))
+            assert all(lo[i] <= i and hi[i] >= i + 1 for i in range(nev)), (k, lo, hi)
+            apply_M = lambda v: f.delta[:, None] * v + 2.0 * (f.L @ (f.L.T @ v))
+            normH = float(f.delta.max() + 2.0 * np.linalg.norm(f.L, 2) ** 2)   # >= ||M||_2 >= ||K||_2
+            res = h_residual(lambda v: f.delta[:, None] * v, apply_M, X, Y, lam, normH)
+        assert res.max() <= 1e-8, (k, res.max())
+        assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12, k
+
+
+def test_request_larger_than_the_budget_fails_without_blocking():
+    """Two concurrent requests whose footprint alone exceeds what the budget
+    leaves beside the operator: both report LREP_ENOMEM (no request waits for
+    memory that can never come), and lrep_finalize returns."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    n = 1024
+    K, M, _ = gen.dense_operator(n, 1202)
+    ctx = L.lrep_init(0, 2 * n * n * 8 + (1 << 20))   # the operator and 1 MiB
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    outs, tickets = [], []
+    for i in range(2):
+        lam, X, Y = np.zeros(8), np.zeros((n, 8), order="F"), np.zeros((n, 8), order="F")
+        opts = L.make_opts(window=16)
+        outs.append((lam, X, Y, opts))
+        tickets.append(L.lrep_submit(ctx, op, 8, 16, 1e-8, opts, lam, X, Y))
+    deadline = time.time() + 60
+    rcs = {}
+    while len(rcs) < 2 and time.time() < deadline:
+        for t in tickets:
+            if t not in rcs:
+                rc, _ = L.lrep_poll(ctx, t)
+                if rc != L.LREP_EAGAIN:
+                    rcs[t] = rc
+        time.sleep(0.005)
+    assert sorted(rcs.values()) == [L.LREP_ENOMEM, L.LREP_ENOMEM], rcs
+    L.lrep_destroy_op(op)
+    t0 = time.time()
+    L.lrep_finalize(ctx)
+    assert time.time() - t0 < 30
 
 
 def test_budget_admission_queues_and_matches():
@@ -135,7 +201,7 @@ def test_budget_admission_queues_and_matches():
 
 
 def test_cancel_queued_request(served):
-    ctx, ops, sizes, inits, alone = served
+    ctx, ops, sizes, inits, alone, _ = served
     # fill the workers, then cancel the last request while it is still queued
     jobs = []
     for i in range(6):

@@ -213,3 +213,16 @@ def test_not_converged_returns_prefix():
     assert not res.converged and res.iterations == 2
     with pytest.raises(oracle.NotConvergedError):
         _solve(oracle.DenseOperator(K, M), 8, 8, 1e-12, maxit=2, raise_on_maxit=True)
+
+
+def test_dense_spectrum_torch_form_matches_the_numpy_form():
+    """The PyTorch CPU form of the dense closed form (used for n = 32768)
+    gives the NumPy form's eigenvalues, also with exact zeros in m, and the
+    torch QR of the generator gives the same spectrum as the host QR."""
+    f = gen.dense_factors(300, 17, n_zero_m=3)
+    a = exact.dense_spectrum_smallest(f.q1, f.k, f.q2, f.m, 20)
+    b = exact.dense_spectrum_smallest_torch(f.q1, f.k, f.q2, f.m, 20)
+    np.testing.assert_allclose(b, a, rtol=1e-13)
+    np.testing.assert_allclose(a, exact.dense_spectrum(f.q1, f.k, f.q2, f.m, 20), rtol=1e-12)
+    q1, k, q2, m = gen.dense_factors_torch(300, 17, "cpu", n_zero_m=3)
+    np.testing.assert_allclose(exact.dense_spectrum_smallest_torch(q1, k, q2, m, 20), a, rtol=1e-12)
