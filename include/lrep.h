@@ -233,6 +233,22 @@ int lrep_set_nullspace(lrep_op_t op, int64_t r, const double* X0, int64_t ld, in
 int lrep_xy_to_uv(lrep_ctx_t ctx, int64_t n, int64_t nev, const double* X, const double* Y, int64_t ldxy, double* U,
                   double* V, int64_t lduv);
 
+/* Allocation-free block apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): Y = K X (which = 0) or Y = M X (which = 1, after the
+ * role exchange of LREP_NULL_ON_M), the products of lrep_test_apply, with X
+ * and Y device arrays of n x cols (ld n, n = the operator's size) on the
+ * operator's device.  Every intermediate lives in one fixed 40 MiB device
+ * array of the library (one per device, held until the process ends); the
+ * call allocates nothing and returns when Y is complete (the context's
+ * stream is synchronised).  Calls on one device share that array: calls that
+ * overlap on one device (other streams or contexts) race.  Limits: dense
+ * operators n <= 73728 for cols <= 32; low-rank M applies rank * cols <=
+ * 524288; beyond them LREP_EINVAL with the reason in lrep_last_error.
+ * Errors: LREP_EINVAL, LREP_EDEVICE (also when the operator's callback
+ * fails). */
+int lrep_apply_noalloc(lrep_op_t op, int which, int cols, const double* X, double* Y);
+
 /* Compute the null space instead of declaring it (the remark on computing the
  * generalized null space, Section 2.2: the zero eigenvectors of the
  * semidefinite operator A = K, or M with LREP_NULL_ON_M).  rmax (1..64,

@@ -143,6 +143,7 @@ _SIGS = {
     "lrep_test_small_lrep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _I64, _P, _P, _P]),
     "lrep_test_block_mgs": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "lrep_test_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lrep_apply_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "lrep_test_cg": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(_I64)]),
     "lrep_test_convert16": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _I64, _P]),
@@ -445,6 +446,16 @@ def lrep_test_block_mgs(ctx, X, Y):
     _check(lib().lrep_test_block_mgs(ctx, X.shape[0], X.shape[1], px, py, ctypes.byref(k)), ctx,
            "lrep_test_block_mgs")
     return k.value
+
+
+def lrep_apply_noalloc(op, which, X, Y, ctx=None):
+    """Y = K X (which 0) or M X (which 1) through the allocation-free entry
+    point; X, Y device tensors of n x cols in column-major layout."""
+    px, ldx, _ = colmajor(X)
+    py, ldy, _ = colmajor(Y)
+    if ldx != X.shape[0] or ldy != Y.shape[0] or X.shape != Y.shape:
+        raise ValueError("X and Y must be n x cols with leading dimension n")
+    return _check(lib().lrep_apply_noalloc(op, which, X.shape[1], px, py), ctx, "lrep_apply_noalloc")
 
 
 def lrep_test_cg(op, which, B, X, tol=1e-2, maxit=20, fused=0):

@@ -198,7 +198,7 @@ int lrep_init(lrep_ctx_t* out, int device, size_t hbm_budget_bytes, void* hip_st
     auto* c = new lrep_ctx_s();
     c->device = device;
     c->budget = hbm_budget_bytes;
-    if (set_device(c) != LREP_OK) {
+    if (set_device(c) != LREP_OK || noalloc_setup(device) != LREP_OK) {
         delete c;
         return LREP_EDEVICE;
     }

@@ -160,5 +160,8 @@ int op_apply(Op* op, hipStream_t st, int which, const double* X, int64_t ldx, in
              double* work, size_t work_elems, double* small, const int* active_flag,
              hipEvent_t* ev = nullptr, double* pq = nullptr);
 bool op_apply_has_pq(const Op* op, int which, const double* X, int64_t ldx, int cols);
+// device address of the allocation-free apply's fixed scratch array, looked
+// up once per device (noalloc.hip); called by lrep_init with the device current
+int noalloc_setup(int device);
 
 }  // namespace lrep
