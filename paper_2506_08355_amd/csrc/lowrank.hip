@@ -591,30 +591,31 @@ __global__ __launch_bounds__(256) void fcg_init_kernel(int n, int nch, const dou
 // arrives last, the finishing step: rho, beta, the relative residual test,
 // T = S + beta T, c, alpha = rho / (c + 2 |T|^2) and any_active.  With init,
 // the records hold (|b|^2, b^T diag(delta) b) and T = L^T b is already in place.
-__global__ __launch_bounds__(512) void fcg_fin_kernel(int w, int ldr, int nS, int nrec, int stride,
-                                                      const double* __restrict__ rec, double* __restrict__ red,
-                                                      CgState s, double tol, int init) {
-    __shared__ double ph[16][32];
+constexpr int FIN_PH = 32;   // record phases per element in fcg_fin_kernel (<= 8 records each)
+
+__global__ __launch_bounds__(32 * FIN_PH) void fcg_fin_kernel(int w, int ldr, int nS, int nrec, int stride,
+                                                             const double* __restrict__ rec,
+                                                             double* __restrict__ red, CgState s, double tol,
+                                                             int init) {
+    __shared__ double ph[FIN_PH][32];
     __shared__ double cb[32];
     __shared__ int cact[32];
     if (!init && *s.any_active == 0) return;
     const int tid = threadIdx.x, x = tid % 32, q = tid / 32;
     const int e = blockIdx.x * 32 + x;
-    double s0 = 0.0, s1 = 0.0;
-    if (e < stride) {
-        int k = q;
-        for (; k + 16 < nrec; k += 32) {
-            s0 += rec[(int64_t)k * stride + e];
-            s1 += rec[(int64_t)(k + 16) * stride + e];
-        }
-        if (k < nrec) s0 += rec[(int64_t)k * stride + e];
+    // records q, q + 32, ... (at most 8: nrec <= 256), all loads issued together
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int k = q + FIN_PH * u;
+        v[u] = (e < stride && k < nrec) ? rec[(int64_t)k * stride + e] : 0.0;
     }
-    ph[q][x] = s0 + s1;
+    ph[q][x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     __syncthreads();
     if (q == 0 && e < stride) {
         double t = ph[0][x];
 #pragma unroll
-        for (int p = 1; p < 16; ++p) t += ph[p][x];
+        for (int p = 1; p < FIN_PH; ++p) t += ph[p][x];
         red[e] = t;
     }
     if (!last_block_arrives(s.ticket, gridDim.x)) return;
@@ -645,16 +646,27 @@ __global__ __launch_bounds__(512) void fcg_fin_kernel(int w, int ldr, int nS, in
         if (j == 0 && na) atomicAdd(s.napplies, na);
     }
     __syncthreads();
+    // T = S + beta T and |T|^2 for the active columns: rows q, q + 32, ... (<= 8)
     double t2 = 0.0;
     if (ldr > 0 && x < w && cact[x]) {
-        for (int k = q; k < ldr; k += 16) {
-            double* tp = s.T + (int64_t)k * 32 + x;
-            double tn = *tp;
-            if (!init) {
-                tn = fma(cb[x], tn, red[k * 32 + x]);
-                *tp = tn;
+        double tv[8], sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = q + FIN_PH * u;
+            tv[u] = k < ldr ? s.T[(int64_t)k * 32 + x] : 0.0;
+            sv[u] = (!init && k < ldr) ? red[k * 32 + x] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = q + FIN_PH * u;
+            if (k < ldr) {
+                double tn = tv[u];
+                if (!init) {
+                    tn = fma(cb[x], tn, sv[u]);
+                    s.T[(int64_t)k * 32 + x] = tn;
+                }
+                t2 = fma(tn, tn, t2);
             }
-            t2 = fma(tn, tn, t2);
         }
     }
     ph[q][x] = t2;
@@ -663,7 +675,7 @@ __global__ __launch_bounds__(512) void fcg_fin_kernel(int w, int ldr, int nS, in
         const int j = tid;
         double tt = ph[0][j];
 #pragma unroll
-        for (int p = 1; p < 16; ++p) tt += ph[p][j];
+        for (int p = 1; p < FIN_PH; ++p) tt += ph[p][j];
         int act = cact[j];
         double al = 0.0;
         if (act) {
@@ -777,7 +789,8 @@ hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delt
         hipLaunchKernelGGL(lr_reduce_kernel, dim3(8192 / 32), dim3(32 * RED_PH), 0, st, ldr, nchunk, part, 1.0, s.T,
                            nullptr);
     }
-    hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(512), 0, st, w, ldr, 0, nch, FREC, rec, red, s, tol, 1);
+    hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, w, ldr, 0, nch, FREC, rec, red, s,
+                       tol, 1);
     return hipGetLastError();
 }
 
@@ -800,15 +813,16 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(256), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
                            s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, flag_log);
         if (ev) (void)hipEventRecord(ev[1], st);
-        hipLaunchKernelGGL(fcg_fin_kernel, dim3((stride + 31) / 32), dim3(512), 0, st, w, ldr, ldr * 32, ngrid, stride,
-                           rec, red, s, tol, 0);
+        hipLaunchKernelGGL(fcg_fin_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, w, ldr, ldr * 32, ngrid,
+                           stride, rec, red, s, tol, 0);
     } else {
         const int nch = fcg_chunks(n, w);
         double* rec = work;
         double* red = work + (size_t)nch * FREC;
         hipLaunchKernelGGL(fcg_pass_K_kernel, dim3(nch, w), dim3(256), 0, st, n, nch, delta, s.X, s.R, s.P, s.alpha,
                            s.beta, s.active, s.any_active, rec);
-        hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(512), 0, st, w, 0, 0, nch, FREC, rec, red, s, tol, 0);
+        hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, w, 0, 0, nch, FREC, rec, red, s,
+                           tol, 0);
     }
     return hipGetLastError();
 }

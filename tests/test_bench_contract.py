@@ -18,9 +18,20 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""
 
 
-def test_traffic_summary_matches_the_kernel_source():
+def test_traffic_summaries_exist_and_match_their_kernel_source():
+    """Every workload with a counter summary names the source it was taken on;
+    the summary is used only while that source is unchanged, and then holds a
+    plausible per-launch figure (between the algorithmic bytes and 1.5x)."""
+    import hashlib
     import bench
     t = bench.measured_traffic("dense8192")
     assert t is not None, "profiles/apply_stream_kernel.dense8192.traffic.md was taken on another apply.hip"
-    assert 5.0e8 < t < 7.0e8
-    assert bench.measured_traffic("casida262144") is None
+    assert 5.41e8 <= t < 1.5 * 5.41e8
+    for workload, (fname, src, key) in bench.TRAFFIC.items():
+        with open(os.path.join(ROOT, "profiles", fname)) as fh:
+            text = fh.read()
+        assert key + ":" in text and "traffic_bytes_per_launch:" in text, fname
+        with open(os.path.join(bench.CSRC, src), "rb") as fh:
+            same = hashlib.sha256(fh.read()).hexdigest() in text
+        assert (bench.measured_traffic(workload) is not None) == same, workload
+    assert bench.measured_traffic("dense32768") is None
