@@ -587,20 +587,17 @@ __global__ __launch_bounds__(256) void fcg_init_kernel(int n, int nch, const dou
 }
 
 // Fixed-order sum of the workgroup records (nrec records of `stride` doubles:
-// S = L^T r in the first nS, then the column sums), then, in the block that
-// arrives last, the finishing step: rho, beta, the relative residual test,
+// S = L^T r in the first nS, then the column sums) into red; then the
+// finishing step (fcg_finish_kernel): rho, beta, the relative residual test,
 // T = S + beta T, c, alpha = rho / (c + 2 |T|^2) and any_active.  With init,
 // the records hold (|b|^2, b^T diag(delta) b) and T = L^T b is already in place.
-constexpr int FIN_PH = 32;   // record phases per element in fcg_fin_kernel (<= 8 records each)
+constexpr int FIN_PH = 32;   // record phases per element in fcg_reduce_kernel (<= 8 records each)
 
-__global__ __launch_bounds__(32 * FIN_PH) void fcg_fin_kernel(int w, int ldr, int nS, int nrec, int stride,
-                                                             const double* __restrict__ rec,
-                                                             double* __restrict__ red, CgState s, double tol,
-                                                             int init) {
+__global__ __launch_bounds__(32 * FIN_PH) void fcg_reduce_kernel(int nrec, int stride, const double* __restrict__ rec,
+                                                                double* __restrict__ red, const int* __restrict__ any,
+                                                                int init) {
     __shared__ double ph[FIN_PH][32];
-    __shared__ double cb[32];
-    __shared__ int cact[32];
-    if (!init && *s.any_active == 0) return;
+    if (!init && *any == 0) return;
     const int tid = threadIdx.x, x = tid % 32, q = tid / 32;
     const int e = blockIdx.x * 32 + x;
     // records q, q + 32, ... (at most 8: nrec <= 256), all loads issued together
@@ -618,8 +615,19 @@ __global__ __launch_bounds__(32 * FIN_PH) void fcg_fin_kernel(int w, int ldr, in
         for (int p = 1; p < FIN_PH; ++p) t += ph[p][x];
         red[e] = t;
     }
-    if (!last_block_arrives(s.ticket, gridDim.x)) return;
-    // finishing step
+}
+
+// The finishing step from the reduced sums (one workgroup; the launch boundary
+// after fcg_reduce_kernel makes its sums visible -- a last-arriving-block
+// finish cost each of the 260 reducing workgroups a device-scope release)
+__global__ __launch_bounds__(32 * FIN_PH) void fcg_finish_kernel(int w, int ldr, int nS,
+                                                                const double* __restrict__ red, CgState s,
+                                                                double tol, int init) {
+    __shared__ double ph[FIN_PH][32];
+    __shared__ double cb[32];
+    __shared__ int cact[32];
+    if (!init && *s.any_active == 0) return;
+    const int tid = threadIdx.x, x = tid % 32, q = tid / 32;
     if (tid < 32) {
         const int j = tid;
         int act = 0, applied = 0;
@@ -770,7 +778,7 @@ size_t fused_cg_work_elems(int n, int r, int w) {
 
 hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr, const CgState& s,
                          const double* B, int64_t ldb, double tol, double* work, size_t work_elems) {
-    if (n < 2 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
+    if (n < 64 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
         work_elems < fused_cg_work_elems(n, Lr ? r : 0, w))
         return hipErrorInvalidValue;
     const int nch = fcg_chunks(n, w);
@@ -789,15 +797,16 @@ hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delt
         hipLaunchKernelGGL(lr_reduce_kernel, dim3(8192 / 32), dim3(32 * RED_PH), 0, st, ldr, nchunk, part, 1.0, s.T,
                            nullptr);
     }
-    hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, w, ldr, 0, nch, FREC, rec, red, s,
-                       tol, 1);
+    hipLaunchKernelGGL(fcg_reduce_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, nch, FREC, rec, red,
+                       s.any_active, 1);
+    hipLaunchKernelGGL(fcg_finish_kernel, dim3(1), dim3(32 * FIN_PH), 0, st, w, ldr, 0, red, s, tol, 1);
     return hipGetLastError();
 }
 
 hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                          const CgState& s, double tol, double* work, size_t work_elems, hipEvent_t* ev,
                          int* flag_log) {
-    if (n < 2 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
+    if (n < 64 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
         work_elems < fused_cg_work_elems(n, Lr ? r : 0, w) || (reinterpret_cast<uintptr_t>(Lr) & 15))
         return hipErrorInvalidValue;
     if (Lr) {
@@ -813,16 +822,18 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(256), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
                            s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, flag_log);
         if (ev) (void)hipEventRecord(ev[1], st);
-        hipLaunchKernelGGL(fcg_fin_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, w, ldr, ldr * 32, ngrid,
-                           stride, rec, red, s, tol, 0);
+        hipLaunchKernelGGL(fcg_reduce_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, ngrid, stride, rec,
+                           red, s.any_active, 0);
+        hipLaunchKernelGGL(fcg_finish_kernel, dim3(1), dim3(32 * FIN_PH), 0, st, w, ldr, ldr * 32, red, s, tol, 0);
     } else {
         const int nch = fcg_chunks(n, w);
         double* rec = work;
         double* red = work + (size_t)nch * FREC;
         hipLaunchKernelGGL(fcg_pass_K_kernel, dim3(nch, w), dim3(256), 0, st, n, nch, delta, s.X, s.R, s.P, s.alpha,
                            s.beta, s.active, s.any_active, rec);
-        hipLaunchKernelGGL(fcg_fin_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, w, 0, 0, nch, FREC, rec, red, s,
-                           tol, 0);
+        hipLaunchKernelGGL(fcg_reduce_kernel, dim3(FREC / 32), dim3(32 * FIN_PH), 0, st, nch, FREC, rec, red,
+                           s.any_active, 0);
+        hipLaunchKernelGGL(fcg_finish_kernel, dim3(1), dim3(32 * FIN_PH), 0, st, w, 0, 0, red, s, tol, 0);
     }
     return hipGetLastError();
 }

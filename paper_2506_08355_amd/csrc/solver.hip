@@ -355,7 +355,7 @@ struct Solver {
     // low-rank operators: the fused CG (one pass over the rows per step, L
     // read once): 1 for the diagonal operator, 2 for diag + 2 L L^T, else 0
     int fused_cg_kind(int which, int nw) const {
-        if (op->kind != 1 || nw < 1 || nw > 32 || (n & 1) || o.fused_cg < 0 ||
+        if (op->kind != 1 || nw < 1 || nw > 32 || n < 64 || (n & 1) || o.fused_cg < 0 ||
             (reinterpret_cast<uintptr_t>(op->delta) & 15))
             return 0;
         const bool useK = (which == 0) != op->null_on_M();
