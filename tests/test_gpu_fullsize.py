@@ -9,9 +9,13 @@ workloads:
                        F = diag(sqrt k) Q1^T Q2 diag(sqrt m));
   zero variant         the same with 8 exact zeros in m, plus the
                        biorthogonality to the generalized null space;
-  Casida n = 262144    sampled eigenvalues bracketed by the oracle's
+  Casida n = 262144    every eigenvalue bracketed by the oracle's
                        Haynsworth inertia count (no eigenvalue skipped, each
-                       sampled one within 1e-10 relative of the k-th);
+                       within 1e-10 relative of the k-th);
+  dense n = 32768      (mixed precision) all 64 eigenvalues against the
+                       oracle's exact spectrum, stored by
+                       tests/golden/make_dense32768_spectrum.py, for the
+                       FP64, BF16 and FP16 CG applies, per-pair errors printed;
 and, for all, the FP64 residual ||H z - lambda z|| / (||H|| ||z||) <= 1e-8
 and max |Y^T X - I| <= 1e-12, evaluated on the host.
 """
@@ -162,3 +166,56 @@ def test_config2_zero_variant_found_null_space(ctx):
     assert res.max() <= 1e-8, res.max()
     assert np.abs(X.T @ Y - np.eye(nev)).max() <= 1e-12
     assert np.abs(q2[:, m == 0.0].T @ X).max() <= 1e-10
+
+
+GOLDEN32768 = "dense32768_seed1004_spectrum.txt"
+
+
+@pytest.fixture(scope="module")
+def dense32768(ctx):
+    """The n = 32768 dense workload (seed 1004) on the device, borrowed by
+    the operator (16 GiB of FP64 operators), and the oracle's spectrum."""
+    import os
+    from conftest import GOLDEN, load_golden
+    if not os.path.exists(os.path.join(GOLDEN, GOLDEN32768)):
+        pytest.skip("the n = 32768 spectrum has not been generated (tests/golden/make_dense32768_spectrum.py)")
+    ref = load_golden(GOLDEN32768)[:, 1]
+    n = 32768
+    print(f"[fullsize] dense n={n} generating", flush=True)
+    Kd, Md, k, m = gen.dense_operator_device(n, 1004, "cuda:0")
+    op = L.lrep_create_dense(ctx, Kd.T, Md.T, L.LREP_BORROW)
+    yield op, Kd, Md, float(max(k.max(), m.max())), ref
+    L.lrep_destroy_op(op)
+    del Kd, Md
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp64", "bf16_cg", "fp16_cg"])
+def test_config4_dense32768_full_size(ctx, dense32768, precision):
+    """The mixed-precision configuration at its own size: n = 32768, nev 64,
+    block 64, window 32, tol 1e-10, the CG applies of Step 6 in FP64, BF16
+    or FP16 (FP32 accumulation), everything else FP64.  Every eigenvalue
+    within 1e-10 relative of the oracle's exact spectrum (the error of each
+    pair is printed), residual <= 1e-8 and max |X^T Y - I| <= 1e-12 (device
+    FP64 products, independent of the library)."""
+    op, Kd, Md, normH, ref = dense32768
+    n, nev, block, window, tol = 32768, 64, 64, 32, 1e-10
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    print(f"[fullsize] dense n={n} precision={precision}", flush=True)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U, precision=precision)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    err = np.abs(lam - ref[:nev]) / ref[:nev]
+    print(f"[fullsize] precision={precision} iterations {st.iterations}; relative eigenvalue error per pair: "
+          + " ".join(f"{e:.1e}" for e in err), flush=True)
+    assert err.max() <= 1e-10, err.max()
+    Xd, Yd = torch.from_numpy(X).to("cuda:0"), torch.from_numpy(Y).to("cuda:0")
+    ld = torch.from_numpy(lam).to("cuda:0")
+    with torch.no_grad():
+        R1 = Kd @ Xd - Yd * ld
+        R2 = Md @ Yd - Xd * ld
+        res = torch.sqrt((R1 ** 2).sum(0) + (R2 ** 2).sum(0)) / (normH * torch.sqrt((Xd ** 2).sum(0) + (Yd ** 2).sum(0)))
+        bi = float((Xd.T @ Yd - torch.eye(nev, dtype=torch.float64, device="cuda:0")).abs().max())
+    print(f"[fullsize] precision={precision} max residual {float(res.max()):.2e}, max |X^T Y - I| {bi:.2e}",
+          flush=True)
+    assert float(res.max()) <= 1e-8
+    assert bi <= 1e-12
