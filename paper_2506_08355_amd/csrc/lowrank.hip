@@ -323,20 +323,26 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
                                                          const double* __restrict__ beta,
                                                          const int* __restrict__ active, const int* __restrict__ any,
                                                          double* __restrict__ rec, int stride,
+                                                         double* __restrict__ sink,
                                                          int* __restrict__ flag_log) {
     const int on = *any;
     if (flag_log && blockIdx.x == 0 && threadIdx.x == 0) *flag_log = on;
     if (on == 0) return;
     __shared__ double sl[4 * FT * FLS];   // wavefront slices of L; then the partial products
-    __shared__ double stt[256 * FMS];     // T, k-major
+    __shared__ double stt[256 * FMS];     // T, k-major (rows from ldr on are zero)
     __shared__ double sr[FT * FMS];       // r of the tile
     const int tid = threadIdx.x, lane = tid % WAVE, v = tid / WAVE, c = lane % 16, g = lane / 16;
-    const bool hasL = 64 * v < ldr;   // wavefront-uniform (ldr is a multiple of 64)
+    // wavefronts beyond ldr / 64 stream a copy of the first column block and
+    // multiply it by the zero rows of T: every wavefront runs the same
+    // branch-free code, so the compiler can count the loads in flight exactly
+    const bool hasL = 64 * v < ldr;
     double* slv = sl + v * FT * FLS;
-    for (int idx = tid; idx < ldr * 32; idx += 256) stt[(idx >> 5) * FMS + (idx & 31)] = T[idx];
+    for (int idx = tid; idx < 256 * 32; idx += 256)
+        stt[(idx >> 5) * FMS + (idx & 31)] = idx < ldr * 32 ? T[idx] : 0.0;
     // epilogue: thread -> column ej, rows 4 eq .. 4 eq + 3 of the tile
     const int ej = tid >> 3, eq = tid & 7;
     const bool ecol = ej < w;
+    const int ejc = ecol ? ej : 0;
     const bool eact = ecol && active[ej] != 0;
     const double ea = eact ? alpha[ej] : 0.0, eb = eact ? beta[ej] : 0.0;
     double srho = 0.0, sa = 0.0, sb = 0.0;
@@ -345,60 +351,77 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
     for (int t = 0; t < 4; ++t) acc2[t][0] = acc2[t][1] = d4{0.0, 0.0, 0.0, 0.0};
     const int ntile = (n + FT - 1) / FT;
     const int tbeg = blockIdx.x * tpw, tend = min(ntile, tbeg + tpw);
-    const double* lbase = Lr + 64 * v + c;
+    const double* lbase = Lr + (hasL ? 64 * v : 0) + c;
     __syncthreads();
 
+    // A tile's slice (row 4 s + g, column 16 t + c in lane (g, c)).  Rows
+    // beyond n read row n - 1 and tiles beyond the workgroup's last read its
+    // last tile (an L2 hit); results of those rows are masked in the epilogue.
+    // No select on loaded values: nothing waits for them before their use.
     auto loadL = [&](double (&a)[8][4], int tile) {
-        if (!hasL || tile >= tend) return;
+        const int tl = min(tile, tend - 1);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const int row = tile * FT + 4 * s + g;
-            const bool ok = row < n;
-            const double* lp = lbase + (int64_t)(ok ? row : 0) * ldr;
+            const int row = min(tl * FT + 4 * s + g, n - 1);
+            const double* lp = lbase + (int64_t)row * ldr;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double x = lp[16 * t];
-                a[s][t] = ok ? x : 0.0;
-            }
+            for (int t = 0; t < 4; ++t) a[s][t] = lp[16 * t];
         }
     };
+    // A tile's x, r, p, delta for the epilogue thread (rows 4 eq .. 4 eq + 3,
+    // column ej): 16-byte loads at a clamped, aligned position (n is even, so
+    // the last group of a ragged tail starts 0 or 2 rows early); the masks are
+    // applied where the values are used.
+    auto loadV = [&](double2 (&vv)[8], int tile) {
+        const int tl = min(tile, tend - 1);
+        const int er2 = min(tl * FT + 4 * eq, n - 4);
+        const int64_t o = (int64_t)ejc * n + er2;
+        vv[0] = *reinterpret_cast<const double2*>(X + o);
+        vv[1] = *reinterpret_cast<const double2*>(X + o + 2);
+        vv[2] = *reinterpret_cast<const double2*>(R + o);
+        vv[3] = *reinterpret_cast<const double2*>(R + o + 2);
+        vv[4] = *reinterpret_cast<const double2*>(P + o);
+        vv[5] = *reinterpret_cast<const double2*>(P + o + 2);
+        vv[6] = *reinterpret_cast<const double2*>(delta + er2);
+        vv[7] = *reinterpret_cast<const double2*>(delta + er2 + 2);
+    };
 
-    auto step = [&](double (&cur)[8][4], double (&nxt)[8][4], int tile) {
+    // Stores of a tile's x, r, p: kept in registers and issued at the start of
+    // the next tile, before that tile's prefetch, always six 16-byte stores
+    // per thread (rows of a column that is not active, or beyond n, go to this
+    // thread's slot of `sink` instead): every path issues the same memory
+    // operations in the same order, so each wait the compiler places names
+    // the oldest loads in flight only.
+    double* const mysink = sink + ((int64_t)blockIdx.x * 256 + tid) * 12;
+    double2 st[6];
+    // where the pending group goes: rows 0, 1 at px, pr, pp, rows 2, 3 at
+    // + hoff (2; 0 for the group that straddles n, whose upper pair then
+    // repeats the lower one)
+    double *px = mysink, *pr = mysink + 4, *pp = mysink + 8;
+    int hoff = 2;
+    auto flush = [&]() {
+        *reinterpret_cast<double2*>(px) = st[0];
+        *reinterpret_cast<double2*>(px + hoff) = st[1];
+        *reinterpret_cast<double2*>(pr) = st[2];
+        *reinterpret_cast<double2*>(pr + hoff) = st[3];
+        *reinterpret_cast<double2*>(pp) = st[4];
+        *reinterpret_cast<double2*>(pp + hoff) = st[5];
+    };
+
+    // one tile: cur holds its slice, vc its vectors; the next tile's slice goes
+    // to nxt right after the slice is in LDS and the previous tile's stores,
+    // its vectors to vn after the epilogue
+    auto step = [&](double (&cur)[8][4], double (&nxt)[8][4], double2 (&vc)[8], double2 (&vn)[8], int tile) {
         const int er = tile * FT + 4 * eq;
-        // (1) this wavefront's slice into LDS
-        if (hasL) {
+        // (1) this wavefront's slice into LDS, the previous tile's stores, the next tile's slice
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < 8; ++s)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) slv[(4 * s + g) * FLS + 16 * t + c] = cur[s][t];
-        }
-        // next tile's slice, and this tile's vectors for the epilogue
+            for (int t = 0; t < 4; ++t) slv[(4 * s + g) * FLS + 16 * t + c] = cur[s][t];
+        flush();
         loadL(nxt, tile + 1);
-        double xv[4], rv[4], pv[4], dv[4];
-        const int64_t o = (int64_t)ej * n + er;
-        const bool full = er + 3 < n;
-        if (ecol && full) {
-            const double2 x0 = *reinterpret_cast<const double2*>(X + o), x1 = *reinterpret_cast<const double2*>(X + o + 2);
-            const double2 r0 = *reinterpret_cast<const double2*>(R + o), r1 = *reinterpret_cast<const double2*>(R + o + 2);
-            const double2 p0 = *reinterpret_cast<const double2*>(P + o), p1 = *reinterpret_cast<const double2*>(P + o + 2);
-            const double2 d0 = *reinterpret_cast<const double2*>(delta + er),
-                          d1 = *reinterpret_cast<const double2*>(delta + er + 2);
-            xv[0] = x0.x; xv[1] = x0.y; xv[2] = x1.x; xv[3] = x1.y;
-            rv[0] = r0.x; rv[1] = r0.y; rv[2] = r1.x; rv[3] = r1.y;
-            pv[0] = p0.x; pv[1] = p0.y; pv[2] = p1.x; pv[3] = p1.y;
-            dv[0] = d0.x; dv[1] = d0.y; dv[2] = d1.x; dv[3] = d1.y;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const bool ok = ecol && er + i < n;
-                xv[i] = ok ? X[o + i] : 0.0;
-                rv[i] = ok ? R[o + i] : 0.0;
-                pv[i] = ok ? P[o + i] : 0.0;
-                dv[i] = ok ? delta[er + i] : 0.0;
-            }
-        }
         // (2) partial product L_slice T_slice: row 16 rb + c, k = 4 ks + g
-        if (hasL) {
+        {
             d4 acc1[2][2];
             acc1[0][0] = acc1[0][1] = acc1[1][0] = acc1[1][1] = d4{0.0, 0.0, 0.0, 0.0};
             const double* tb = stt + (64 * v + g) * FMS + c;
@@ -421,44 +444,47 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
                     for (int i = 0; i < 4; ++i) slv[(16 * rb + 4 * i + g) * FMS + 16 * jb + c] = acc1[rb][jb][i];
         }
         __syncthreads();
-        // (3) epilogue
+        // (3) epilogue.  Rows beyond n are masked to zero.  The one group that
+        // straddles n (n = 4 q + 2) was loaded two rows early: its two rows
+        // are the upper halves of the loads.
+        const bool half = er + 2 == n;
+        const double xs[4] = {half ? vc[1].x : vc[0].x, half ? vc[1].y : vc[0].y, vc[1].x, vc[1].y};
+        const double rs[4] = {half ? vc[3].x : vc[2].x, half ? vc[3].y : vc[2].y, vc[3].x, vc[3].y};
+        const double ps[4] = {half ? vc[5].x : vc[4].x, half ? vc[5].y : vc[4].y, vc[5].x, vc[5].y};
+        const double ds[4] = {half ? vc[7].x : vc[6].x, half ? vc[7].y : vc[6].y, vc[7].x, vc[7].y};
         double lr2 = 0.0, la2 = 0.0, lb2 = 0.0;
+        double xo[4], ro[4], po[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = 4 * eq + i;
-            double m = 0.0;
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv)
-                if (64 * vv < ldr) m += sl[vv * FT * FLS + row * FMS + ej];
-            const double p = fma(eb, pv[i], rv[i]);
-            const double ap = fma(dv[i], p, 2.0 * m);
-            const double rn = fma(-ea, ap, rv[i]);
-            xv[i] = fma(ea, p, xv[i]);
-            rv[i] = rn;
-            pv[i] = p;
+            const bool ok = ecol && er + i < n;
+            const double xv = ok ? xs[i] : 0.0, rv = ok ? rs[i] : 0.0, pv = ok ? ps[i] : 0.0, dv = ok ? ds[i] : 0.0;
+            const double m = ((sl[row * FMS + ej] + sl[FT * FLS + row * FMS + ej]) +
+                              sl[2 * FT * FLS + row * FMS + ej]) + sl[3 * FT * FLS + row * FMS + ej];
+            const double p = fma(eb, pv, rv);
+            const double ap = fma(dv, p, 2.0 * m);
+            const double rn = ok ? fma(-ea, ap, rv) : 0.0;
+            xo[i] = fma(ea, p, xv);
+            ro[i] = rn;
+            po[i] = p;
             lr2 = fma(rn, rn, lr2);
-            la2 = fma(dv[i] * rn, rn, la2);
-            lb2 = fma(dv[i] * rn, p, lb2);
+            la2 = fma(dv * rn, rn, la2);
+            lb2 = fma(dv * rn, p, lb2);
             sr[row * FMS + ej] = eact ? rn : 0.0;
         }
-        if (eact) {
-            if (full) {
-                *reinterpret_cast<double2*>(X + o) = double2{xv[0], xv[1]};
-                *reinterpret_cast<double2*>(X + o + 2) = double2{xv[2], xv[3]};
-                *reinterpret_cast<double2*>(R + o) = double2{rv[0], rv[1]};
-                *reinterpret_cast<double2*>(R + o + 2) = double2{rv[2], rv[3]};
-                *reinterpret_cast<double2*>(P + o) = double2{pv[0], pv[1]};
-                *reinterpret_cast<double2*>(P + o + 2) = double2{pv[2], pv[3]};
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (er + i < n) {
-                        X[o + i] = xv[i];
-                        R[o + i] = rv[i];
-                        P[o + i] = pv[i];
-                    }
-            }
-        }
+        st[0] = double2{xo[0], xo[1]};
+        st[1] = half ? st[0] : double2{xo[2], xo[3]};
+        st[2] = double2{ro[0], ro[1]};
+        st[3] = half ? st[2] : double2{ro[2], ro[3]};
+        st[4] = double2{po[0], po[1]};
+        st[5] = half ? st[4] : double2{po[2], po[3]};
+        const bool real = eact && er < n;
+        const int64_t o = (int64_t)ej * n + er;
+        px = real ? X + o : mysink;
+        pr = real ? R + o : mysink + 4;
+        pp = real ? P + o : mysink + 8;
+        hoff = half ? 0 : 2;
+        loadV(vn, tile + 1);
         // column sums of the tile over its 8 threads (consecutive lanes)
 #pragma unroll
         for (int off = 1; off < 8; off <<= 1) {
@@ -471,25 +497,30 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
         sb += lb2;
         __syncthreads();
         // (4) S += L_slice^T r: k = 64 v + 16 t + c, rows 4 s + g
-        if (hasL) {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const double b0 = sr[(4 * s + g) * FMS + c], b1 = sr[(4 * s + g) * FMS + 16 + c];
+        for (int s = 0; s < 8; ++s) {
+            const double b0 = sr[(4 * s + g) * FMS + c], b1 = sr[(4 * s + g) * FMS + 16 + c];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    acc2[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b0, acc2[t][0], 0, 0, 0);
-                    acc2[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b1, acc2[t][1], 0, 0, 0);
-                }
+            for (int t = 0; t < 4; ++t) {
+                acc2[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b0, acc2[t][0], 0, 0, 0);
+                acc2[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b1, acc2[t][1], 0, 0, 0);
             }
         }
     };
 
     double la[8][4], lb[8][4];
+    double2 va[8], vb[8];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st[k] = double2{0.0, 0.0};
     loadL(la, tbeg);
-    for (int tile = tbeg; tile < tend; tile += 2) {
-        step(la, lb, tile);
-        if (tile + 1 < tend) step(lb, la, tile + 1);
+    loadV(va, tbeg);
+    int tile = tbeg;
+    for (; tile + 1 < tend; tile += 2) {
+        step(la, lb, va, vb, tile);
+        step(lb, la, vb, va, tile + 1);
     }
+    if (tile < tend) step(la, lb, va, vb, tile);
+    flush();
     // the workgroup's record: S (k-major, ldr x 32), then the column sums
     double* out = rec + (int64_t)blockIdx.x * stride;
     if (hasL) {
@@ -770,7 +801,8 @@ size_t fused_cg_work_elems(int n, int r, int w) {
     const size_t stride = ldr * 32 + FREC;
     size_t need = (size_t)fcg_chunks(n, 32) * FREC + FREC;                       // init / diagonal steps
     if (r > 0) {
-        need = std::max(need, (size_t)fcg_groups(n) * stride + stride);          // M steps
+        // M steps: records, their reduction, the pass's store sink (12 doubles a thread)
+        need = std::max(need, (size_t)fcg_groups(n) * stride + stride + (size_t)fcg_groups(n) * 256 * 12);
         need = std::max(need, (size_t)256 * 32 + (size_t)fcg_lty_chunks(n) * 8192 + FREC * 256);   // L^T b
     }
     return need;
@@ -818,9 +850,10 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         const int stride = ldr * 32 + FREC;
         double* rec = work;
         double* red = work + (size_t)ngrid * stride;
+        double* sink = red + stride;
         if (ev) (void)hipEventRecord(ev[0], st);
         hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(256), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
-                           s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, flag_log);
+                           s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, sink, flag_log);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(fcg_reduce_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, ngrid, stride, rec,
                            red, s.any_active, 0);
