@@ -296,25 +296,37 @@ __global__ __launch_bounds__(64) void lr_apply_kernel(int n, int ldr, int w, con
 // twice -- for L^T p and for L (L^T p) -- and streams x, r, p, A p in separate
 // passes.)
 //
-// Pass (fcg_pass_M_kernel): one workgroup per CU (LDS 142 KiB), tiles of 32
-// rows, four wavefronts; wavefront v owns L's columns [64 v, 64 v + 64).  Per
-// tile: (1) the wavefront's 32 x 64 slice of L, loaded one tile ahead into
-// registers with row 4 s + g, column 16 t + c in lane (g = lane / 16,
-// c = lane % 16), goes to LDS; (2) the partial product L_slice T_slice
-// (MFMA, A operand read back from LDS with row on c and column on g) replaces
-// the slice in LDS; (3) after a barrier every thread takes 4 rows of one
-// column: p = r + beta p, A p = delta p + 2 (sum of the four partials in a
-// fixed order), x += alpha p, r -= alpha A p, stores x, r, p, and puts r in
-// LDS; (4) after a barrier each wavefront adds L_slice^T r to its block of S
-// with the slice still in registers (MFMA, row on g).  S and the column sums
-// leave the workgroup once, as one record per workgroup.
+// Pass (fcg_pass_M_kernel): one workgroup of 512 threads per CU (LDS
+// 142 KiB), run as two pipelines of four wavefronts over interleaved tiles of
+// 16 rows; wavefront v of a pipeline owns L's columns [64 v, 64 v + 64).  Per
+// tile j a pipeline runs two phases, each closed by a workgroup barrier:
+//  A  (MFMA) the wavefront's 16 x 64 slice of tile j (rows 4 s + g, columns
+//     32 h + 2 c and 32 h + 2 c + 1 in lane (g, c) = (lane / 16, lane % 16),
+//     16-byte loads) goes to LDS; the partial product L_slice T_slice (A
+//     operand read back with row on c, column on g) is interleaved with
+//     S += L_{j-1}^T r_{j-1} from the previous slice, still in registers
+//     (row on g); the next tile's slice is requested into the registers just
+//     freed, and the partial product replaces the slice in LDS;
+//  B  (vector) every thread takes two rows of one column: p = r + beta p,
+//     A p = delta p + 2 (sum of the four partials in a fixed order),
+//     x += alpha p, r -= alpha A p; x, r, p are stored, r goes to LDS, and the
+//     next tile's vectors are requested.
+// The second pipeline starts one phase late, so that while one pipeline's
+// wavefronts are in their MFMA phase the other's are in their vector phase:
+// the matrix cores and the memory stream see work in every interval.  Only
+// T (read-only) is shared between the pipelines.  At the end the second
+// pipeline hands its block of S and its column sums to the first through LDS,
+// and S and the column sums leave the workgroup as one record.
 // ---------------------------------------------------------------------------
-constexpr int FT = 32;     // rows per tile
-constexpr int FLS = 65;    // LDS stride of a wavefront's slice (32 rows x 64 columns of L)
-constexpr int FMS = 33;    // LDS stride of the 32-column arrays (T, r, partial products)
-constexpr int FREC = 128;  // column sums per record: (rho, a, b, 0) for 32 columns
+constexpr int PT = 16;               // rows per tile
+constexpr int FLS = 65;              // LDS stride of a wavefront's slice (16 rows x 64 columns of L)
+constexpr int FMS = 33;              // LDS stride of the 32-column arrays (T, r, partial products)
+constexpr int PSL = 4 * PT * FLS;    // doubles of a pipeline's slices
+constexpr int PSR = PT * FMS;        // doubles of a pipeline's r
+constexpr int FREC = 128;            // column sums per record: (rho, a, b, 0) for 32 columns
+constexpr int FSINK = 6;             // doubles of the store sink per thread
 
-__global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, int tpw,
+__global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, int tpw,
                                                          const double* __restrict__ Lr,
                                                          const double* __restrict__ delta, double* __restrict__ X,
                                                          double* __restrict__ R, double* __restrict__ P,
@@ -328,200 +340,214 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
     const int on = *any;
     if (flag_log && blockIdx.x == 0 && threadIdx.x == 0) *flag_log = on;
     if (on == 0) return;
-    __shared__ double sl[4 * FT * FLS];   // wavefront slices of L; then the partial products
-    __shared__ double stt[256 * FMS];     // T, k-major (rows from ldr on are zero)
-    __shared__ double sr[FT * FMS];       // r of the tile
-    const int tid = threadIdx.x, lane = tid % WAVE, v = tid / WAVE, c = lane % 16, g = lane / 16;
+    __shared__ double sl[2 * PSL];     // per pipeline: wavefront slices of L, then the partial products
+    __shared__ double stt[256 * FMS];  // T, k-major (rows from ldr on are zero); at the end the hand-over
+    __shared__ double sr[2 * PSR];     // per pipeline: r of the tile
+    const int tid = threadIdx.x;
+    const int pp = __builtin_amdgcn_readfirstlane(tid >> 8);   // pipeline (wavefront-uniform)
+    const int lt = tid & 255, lane = tid % WAVE, v = lt / WAVE, c = lane % 16, g = lane / 16;
+    for (int idx = tid; idx < 256 * 32; idx += 512)
+        stt[(idx >> 5) * FMS + (idx & 31)] = idx < ldr * 32 ? T[idx] : 0.0;
+    // r starts at zero: the first phase A multiplies it by a zero slice
+    for (int idx = tid; idx < 2 * PSR; idx += 512) sr[idx] = 0.0;
+
     // wavefronts beyond ldr / 64 stream a copy of the first column block and
     // multiply it by the zero rows of T: every wavefront runs the same
     // branch-free code, so the compiler can count the loads in flight exactly
     const bool hasL = 64 * v < ldr;
-    double* slv = sl + v * FT * FLS;
-    for (int idx = tid; idx < 256 * 32; idx += 256)
-        stt[(idx >> 5) * FMS + (idx & 31)] = idx < ldr * 32 ? T[idx] : 0.0;
-    // epilogue: thread -> column ej, rows 4 eq .. 4 eq + 3 of the tile
-    const int ej = tid >> 3, eq = tid & 7;
+    const double* lbase = Lr + (hasL ? 64 * v : 0) + 2 * c;
+    double* slp = sl + pp * PSL;          // the pipeline's four slices / partials
+    double* slv = slp + v * PT * FLS;     // this wavefront's
+    double* srp = sr + pp * PSR;
+    // phase B: thread -> column ej, rows 2 eq, 2 eq + 1 of the tile
+    const int ej = lt >> 3, eq = lt & 7;
     const bool ecol = ej < w;
     const int ejc = ecol ? ej : 0;
     const bool eact = ecol && active[ej] != 0;
     const double ea = eact ? alpha[ej] : 0.0, eb = eact ? beta[ej] : 0.0;
+    double* const mysink = sink + ((int64_t)blockIdx.x * 512 + tid) * FSINK;
     double srho = 0.0, sa = 0.0, sb = 0.0;
     d4 acc2[4][2];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc2[t][0] = acc2[t][1] = d4{0.0, 0.0, 0.0, 0.0};
-    const int ntile = (n + FT - 1) / FT;
-    const int tbeg = blockIdx.x * tpw, tend = min(ntile, tbeg + tpw);
-    const double* lbase = Lr + (hasL ? 64 * v : 0) + c;
-    __syncthreads();
 
-    // A tile's slice (row 4 s + g, column 16 t + c in lane (g, c)).  Rows
-    // beyond n read row n - 1 and tiles beyond the workgroup's last read its
-    // last tile (an L2 hit); results of those rows are masked in the epilogue.
-    // No select on loaded values: nothing waits for them before their use.
-    auto loadL = [&](double (&a)[8][4], int tile) {
-        const int tl = min(tile, tend - 1);
+    // this pipeline's tiles: tbeg + pp + 2 j, j < nj
+    const int ntile = (n + PT - 1) / PT;
+    const int tbeg = blockIdx.x * tpw, tend = min(ntile, tbeg + tpw);
+    const int nj = (tend - tbeg - pp + 1) / 2;
+    auto tile_of = [&](int j) { return tbeg + pp + 2 * max(0, min(j, nj - 1)); };
+
+    // A tile's slice; rows beyond n read row n - 1 and tiles beyond the
+    // pipeline's last read its last tile (an L2 hit); those rows are masked
+    // in phase B.  No select on loaded values: nothing waits for them early.
+    auto loadL = [&](double2 (&a)[4][2], int j) {
+        const int tl = tile_of(j);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int row = min(tl * FT + 4 * s + g, n - 1);
+        for (int s = 0; s < 4; ++s) {
+            const int row = min(tl * PT + 4 * s + g, n - 1);
             const double* lp = lbase + (int64_t)row * ldr;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[s][t] = lp[16 * t];
+            for (int h = 0; h < 2; ++h) a[s][h] = *reinterpret_cast<const double2*>(lp + 32 * h);
         }
     };
-    // A tile's x, r, p, delta for the epilogue thread (rows 4 eq .. 4 eq + 3,
-    // column ej): 16-byte loads at a clamped, aligned position (n is even, so
-    // the last group of a ragged tail starts 0 or 2 rows early); the masks are
-    // applied where the values are used.
-    auto loadV = [&](double2 (&vv)[8], int tile) {
-        const int tl = min(tile, tend - 1);
-        const int er2 = min(tl * FT + 4 * eq, n - 4);
-        const int64_t o = (int64_t)ejc * n + er2;
+    // A tile's x, r, p, delta at rows (2 eq, 2 eq + 1): one 16-byte load per
+    // vector, clamped to the last pair (n is even: a pair is inside or beyond n)
+    auto loadV = [&](double2 (&vv)[4], int j) {
+        const int r0 = min(tile_of(j) * PT + 2 * eq, n - 2);
+        const int64_t o = (int64_t)ejc * n + r0;
         vv[0] = *reinterpret_cast<const double2*>(X + o);
-        vv[1] = *reinterpret_cast<const double2*>(X + o + 2);
-        vv[2] = *reinterpret_cast<const double2*>(R + o);
-        vv[3] = *reinterpret_cast<const double2*>(R + o + 2);
-        vv[4] = *reinterpret_cast<const double2*>(P + o);
-        vv[5] = *reinterpret_cast<const double2*>(P + o + 2);
-        vv[6] = *reinterpret_cast<const double2*>(delta + er2);
-        vv[7] = *reinterpret_cast<const double2*>(delta + er2 + 2);
+        vv[1] = *reinterpret_cast<const double2*>(R + o);
+        vv[2] = *reinterpret_cast<const double2*>(P + o);
+        vv[3] = *reinterpret_cast<const double2*>(delta + r0);
     };
-
-    // Stores of a tile's x, r, p: kept in registers and issued at the start of
-    // the next tile, before that tile's prefetch, always six 16-byte stores
-    // per thread (rows of a column that is not active, or beyond n, go to this
-    // thread's slot of `sink` instead): every path issues the same memory
-    // operations in the same order, so each wait the compiler places names
-    // the oldest loads in flight only.
-    double* const mysink = sink + ((int64_t)blockIdx.x * 256 + tid) * 12;
-    double2 st[6];
-    // where the pending group goes: rows 0, 1 at px, pr, pp, rows 2, 3 at
-    // + hoff (2; 0 for the group that straddles n, whose upper pair then
-    // repeats the lower one)
-    double *px = mysink, *pr = mysink + 4, *pp = mysink + 8;
-    int hoff = 2;
-    auto flush = [&]() {
-        *reinterpret_cast<double2*>(px) = st[0];
-        *reinterpret_cast<double2*>(px + hoff) = st[1];
-        *reinterpret_cast<double2*>(pr) = st[2];
-        *reinterpret_cast<double2*>(pr + hoff) = st[3];
-        *reinterpret_cast<double2*>(pp) = st[4];
-        *reinterpret_cast<double2*>(pp + hoff) = st[5];
-    };
-
-    // one tile: cur holds its slice, vc its vectors; the next tile's slice goes
-    // to nxt right after the slice is in LDS and the previous tile's stores,
-    // its vectors to vn after the epilogue
-    auto step = [&](double (&cur)[8][4], double (&nxt)[8][4], double2 (&vc)[8], double2 (&vn)[8], int tile) {
-        const int er = tile * FT + 4 * eq;
-        // (1) this wavefront's slice into LDS, the previous tile's stores, the next tile's slice
+    // S += L_slice^T r (rows 4 s + g): block u of S takes k = 64 v + 32 (u / 2)
+    // + 2 c + u % 2 in its row c, so that item i of its 16 x 16 result is
+    // S row ku(u, i) = 64 v + 32 (u / 2) + 8 i + 2 g + u % 2
+    auto lpart = [](const double2 (&a)[4][2], int s, int u) { return (u & 1) ? a[s][u >> 1].y : a[s][u >> 1].x; };
+    auto stage4 = [&](const double2 (&a)[4][2]) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < 4; ++s) {
+            const double b0 = srp[(4 * s + g) * FMS + c], b1 = srp[(4 * s + g) * FMS + 16 + c];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) slv[(4 * s + g) * FLS + 16 * t + c] = cur[s][t];
-        flush();
-        loadL(nxt, tile + 1);
-        // (2) partial product L_slice T_slice: row 16 rb + c, k = 4 ks + g
-        {
-            d4 acc1[2][2];
-            acc1[0][0] = acc1[0][1] = acc1[1][0] = acc1[1][1] = d4{0.0, 0.0, 0.0, 0.0};
-            const double* tb = stt + (64 * v + g) * FMS + c;
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                const double a0 = slv[c * FLS + 4 * ks + g], a1 = slv[(16 + c) * FLS + 4 * ks + g];
-                const double b0 = tb[4 * ks * FMS], b1 = tb[4 * ks * FMS + 16];
-                acc1[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc1[0][0], 0, 0, 0);
-                acc1[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc1[0][1], 0, 0, 0);
-                acc1[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc1[1][0], 0, 0, 0);
-                acc1[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1[1][1], 0, 0, 0);
+            for (int u = 0; u < 4; ++u) {
+                acc2[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(lpart(a, s, u), b0, acc2[u][0], 0, 0, 0);
+                acc2[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(lpart(a, s, u), b1, acc2[u][1], 0, 0, 0);
             }
-            // the partial product replaces the slice (same wavefront, after its reads);
-            // item i of a 16 x 16 result holds row 4 i + g, column c
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) slv[(16 * rb + 4 * i + g) * FMS + 16 * jb + c] = acc1[rb][jb][i];
         }
-        __syncthreads();
-        // (3) epilogue.  Rows beyond n are masked to zero.  The one group that
-        // straddles n (n = 4 q + 2) was loaded two rows early: its two rows
-        // are the upper halves of the loads.
-        const bool half = er + 2 == n;
-        const double xs[4] = {half ? vc[1].x : vc[0].x, half ? vc[1].y : vc[0].y, vc[1].x, vc[1].y};
-        const double rs[4] = {half ? vc[3].x : vc[2].x, half ? vc[3].y : vc[2].y, vc[3].x, vc[3].y};
-        const double ps[4] = {half ? vc[5].x : vc[4].x, half ? vc[5].y : vc[4].y, vc[5].x, vc[5].y};
-        const double ds[4] = {half ? vc[7].x : vc[6].x, half ? vc[7].y : vc[6].y, vc[7].x, vc[7].y};
-        double lr2 = 0.0, la2 = 0.0, lb2 = 0.0;
-        double xo[4], ro[4], po[4];
+    };
+    auto srow = [&](int u, int i) { return 64 * v + 32 * (u >> 1) + 8 * i + 2 * g + (u & 1); };
+
+    double2 vv[4];
+    // one tile: cur holds its slice, old the previous tile's (zero before the first)
+    auto tile_step = [&](double2 (&cur)[4][2], double2 (&old)[4][2], int j) {
+        // ---- phase A: the slice to LDS; then the partial product L_slice
+        // T_slice (row c, k = 4 ks + g) interleaved with the previous tile's
+        // S += L^T r (slice in registers), so that the LDS reads of the one
+        // hide behind the MFMAs of the other; then the next tile's slice into
+        // the registers just freed
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 4 * eq + i;
-            const bool ok = ecol && er + i < n;
-            const double xv = ok ? xs[i] : 0.0, rv = ok ? rs[i] : 0.0, pv = ok ? ps[i] : 0.0, dv = ok ? ds[i] : 0.0;
-            const double m = ((sl[row * FMS + ej] + sl[FT * FLS + row * FMS + ej]) +
-                              sl[2 * FT * FLS + row * FMS + ej]) + sl[3 * FT * FLS + row * FMS + ej];
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                slv[(4 * s + g) * FLS + 32 * h + 2 * c] = cur[s][h].x;
+                slv[(4 * s + g) * FLS + 32 * h + 2 * c + 1] = cur[s][h].y;
+            }
+        double rb0[4], rb1[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            rb0[s] = srp[(4 * s + g) * FMS + c];
+            rb1[s] = srp[(4 * s + g) * FMS + 16 + c];
+        }
+        d4 acc1[2];
+        acc1[0] = acc1[1] = d4{0.0, 0.0, 0.0, 0.0};
+        const double* tb = stt + (64 * v + g) * FMS + c;
+        // operands of step ks are read one step ahead; the scheduling
+        // barriers keep each step's reads ahead of the previous step's MFMAs
+        double a0 = slv[c * FLS + g], b0 = tb[0], b1 = tb[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const double a0c = a0, b0c = b0, b1c = b1;
+            if (ks < 15) {
+                a0 = slv[c * FLS + 4 * (ks + 1) + g];
+                b0 = tb[4 * (ks + 1) * FMS];
+                b1 = tb[4 * (ks + 1) * FMS + 16];
+            }
+            const int s4 = ks >> 2, t4 = ks & 3;
+            acc1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0c, b0c, acc1[0], 0, 0, 0);
+            acc1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0c, b1c, acc1[1], 0, 0, 0);
+            acc2[t4][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(lpart(old, s4, t4), rb0[s4], acc2[t4][0], 0, 0, 0);
+            acc2[t4][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(lpart(old, s4, t4), rb1[s4], acc2[t4][1], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        loadL(old, j + 1);
+        // the partial product replaces the slice (same wavefront, after its
+        // reads); item i of a 16 x 16 result holds row 4 i + g, column c
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) slv[(4 * i + g) * FMS + 16 * jb + c] = acc1[jb][i];
+        __syncthreads();
+        // ---- phase B: rows 2 eq + i; a pair beyond n computes on zeros, is
+        // masked out of the sums and of r in LDS, and its stores go to the sink
+        const int er = tile_of(j) * PT + 2 * eq;
+        const bool ok = ecol && er < n;
+        const double xs[2] = {vv[0].x, vv[0].y}, rs[2] = {vv[1].x, vv[1].y};
+        const double ps[2] = {vv[2].x, vv[2].y}, ds[2] = {vv[3].x, vv[3].y};
+        double ms[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = 2 * eq + i;
+            ms[i] = ((slp[row * FMS + ej] + slp[PT * FLS + row * FMS + ej]) + slp[2 * PT * FLS + row * FMS + ej]) +
+                    slp[3 * PT * FLS + row * FMS + ej];
+        }
+        // the mask is a factor, not a select: a select on a loaded value lets
+        // the compiler move the load under a branch and wait for it there
+        // (the clamped loads read finite rows, so the product is an exact zero)
+        const double okf = ok ? 1.0 : 0.0;
+        double xo[2], ro[2], po[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double xv = xs[i] * okf, rv = rs[i] * okf, pv = ps[i] * okf, dv = ds[i] * okf;
             const double p = fma(eb, pv, rv);
-            const double ap = fma(dv, p, 2.0 * m);
-            const double rn = ok ? fma(-ea, ap, rv) : 0.0;
+            const double ap = fma(dv, p, 2.0 * ms[i]);
+            const double rn = fma(-ea, ap, rv);
+            const double rm = ok ? rn : 0.0;
             xo[i] = fma(ea, p, xv);
             ro[i] = rn;
             po[i] = p;
-            lr2 = fma(rn, rn, lr2);
-            la2 = fma(dv * rn, rn, la2);
-            lb2 = fma(dv * rn, p, lb2);
-            sr[row * FMS + ej] = eact ? rn : 0.0;
+            srho = fma(rm, rm, srho);
+            sa = fma(dv * rm, rm, sa);
+            sb = fma(dv * rm, p, sb);
+            srp[(2 * eq + i) * FMS + ej] = eact ? rm : 0.0;
         }
-        st[0] = double2{xo[0], xo[1]};
-        st[1] = half ? st[0] : double2{xo[2], xo[3]};
-        st[2] = double2{ro[0], ro[1]};
-        st[3] = half ? st[2] : double2{ro[2], ro[3]};
-        st[4] = double2{po[0], po[1]};
-        st[5] = half ? st[4] : double2{po[2], po[3]};
-        const bool real = eact && er < n;
-        const int64_t o = (int64_t)ej * n + er;
-        px = real ? X + o : mysink;
-        pr = real ? R + o : mysink + 4;
-        pp = real ? P + o : mysink + 8;
-        hoff = half ? 0 : 2;
-        loadV(vn, tile + 1);
-        // column sums of the tile over its 8 threads (consecutive lanes)
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            lr2 += __shfl_xor(lr2, off, WAVE);
-            la2 += __shfl_xor(la2, off, WAVE);
-            lb2 += __shfl_xor(lb2, off, WAVE);
+        {
+            const bool real = eact && er < n;
+            const int64_t o = (int64_t)ej * n + er;
+            *reinterpret_cast<double2*>(real ? X + o : mysink) = double2{xo[0], xo[1]};
+            *reinterpret_cast<double2*>(real ? R + o : mysink + 2) = double2{ro[0], ro[1]};
+            *reinterpret_cast<double2*>(real ? P + o : mysink + 4) = double2{po[0], po[1]};
         }
-        srho += lr2;
-        sa += la2;
-        sb += lb2;
+        loadV(vv, j + 1);
         __syncthreads();
-        // (4) S += L_slice^T r: k = 64 v + 16 t + c, rows 4 s + g
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const double b0 = sr[(4 * s + g) * FMS + c], b1 = sr[(4 * s + g) * FMS + 16 + c];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                acc2[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b0, acc2[t][0], 0, 0, 0);
-                acc2[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s][t], b1, acc2[t][1], 0, 0, 0);
-            }
-        }
     };
 
-    double la[8][4], lb[8][4];
-    double2 va[8], vb[8];
+    double2 la[4][2], lb[4][2];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st[k] = double2{0.0, 0.0};
-    loadL(la, tbeg);
-    loadV(va, tbeg);
-    int tile = tbeg;
-    for (; tile + 1 < tend; tile += 2) {
-        step(la, lb, va, vb, tile);
-        step(lb, la, vb, va, tile + 1);
+    for (int s = 0; s < 4; ++s) lb[s][0] = lb[s][1] = double2{0.0, 0.0};
+    loadL(la, 0);
+    loadV(vv, 0);
+    __syncthreads();
+    // both pipelines pass the same number of barriers: the second one waits
+    // one phase first, the shorter one pads at the end
+    const int nbar = max(2 * ((tend - tbeg + 1) / 2), 1 + 2 * ((tend - tbeg) / 2));
+    if (pp == 1) __syncthreads();
+    int j = 0;
+    for (; j + 1 < nj; j += 2) {
+        tile_step(la, lb, j);
+        tile_step(lb, la, j + 1);
     }
-    if (tile < tend) step(la, lb, va, vb, tile);
-    flush();
-    // the workgroup's record: S (k-major, ldr x 32), then the column sums
+    if (j < nj) tile_step(la, lb, j);
+    // the last tile's S term (its slice is in la when nj is odd, in lb when
+    // nj is even; with no tile at all lb and r are zero)
+    if (nj & 1) stage4(la);
+    else stage4(lb);
+    for (int b = pp + 2 * nj; b < nbar; ++b) __syncthreads();
+
+    // hand-over: T is no longer read (every stage 2 lies before the barriers above)
+    if (pp == 1) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) stt[srow(t, i) * 32 + 16 * jb + c] = acc2[t][jb][i];
+        double* cs1 = sl + PSL + 3 * lt;
+        cs1[0] = srho;
+        cs1[1] = sa;
+        cs1[2] = sb;
+    }
+    __syncthreads();
+    if (pp == 1) return;
     double* out = rec + (int64_t)blockIdx.x * stride;
     if (hasL) {
 #pragma unroll
@@ -529,7 +555,22 @@ __global__ __launch_bounds__(256) void fcg_pass_M_kernel(int n, int ldr, int w, 
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) out[(64 * v + 16 * t + 4 * i + g) * 32 + 16 * jb + c] = acc2[t][jb][i];
+                for (int i = 0; i < 4; ++i) {
+                    const int idx = srow(t, i) * 32 + 16 * jb + c;
+                    out[idx] = acc2[t][jb][i] + stt[idx];
+                }
+    }
+    // column sums: the two pipelines, then the column's 8 threads
+    // (consecutive lanes), each thread's own sum taken over its rows in tile order
+    const double* cs1 = sl + PSL + 3 * lt;
+    srho += cs1[0];
+    sa += cs1[1];
+    sb += cs1[2];
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        srho += __shfl_xor(srho, off, WAVE);
+        sa += __shfl_xor(sa, off, WAVE);
+        sb += __shfl_xor(sb, off, WAVE);
     }
     if (eq == 0) {
         double* cs = out + ldr * 32 + 4 * ej;
@@ -783,7 +824,7 @@ int fcg_chunks(int n, int w) {
     return std::max(1, std::min(nch, 256));
 }
 int fcg_groups(int n) {
-    const int ntile = (n + FT - 1) / FT;
+    const int ntile = (n + PT - 1) / PT;
     return std::min(256, ntile);
 }
 // row chunk of the L^T b pass (a multiple of 2 RU, as in lowrank_apply_M_rows)
@@ -801,8 +842,8 @@ size_t fused_cg_work_elems(int n, int r, int w) {
     const size_t stride = ldr * 32 + FREC;
     size_t need = (size_t)fcg_chunks(n, 32) * FREC + FREC;                       // init / diagonal steps
     if (r > 0) {
-        // M steps: records, their reduction, the pass's store sink (12 doubles a thread)
-        need = std::max(need, (size_t)fcg_groups(n) * stride + stride + (size_t)fcg_groups(n) * 256 * 12);
+        // M steps: records, their reduction, the pass's store sink
+        need = std::max(need, (size_t)fcg_groups(n) * stride + stride + (size_t)fcg_groups(n) * 512 * FSINK);
         need = std::max(need, (size_t)256 * 32 + (size_t)fcg_lty_chunks(n) * 8192 + FREC * 256);   // L^T b
     }
     return need;
@@ -843,7 +884,7 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         return hipErrorInvalidValue;
     if (Lr) {
         const int ldr = (int)lowrank_row_ld(r);
-        const int ntile = (n + FT - 1) / FT;
+        const int ntile = (n + PT - 1) / PT;
         const int nwg = fcg_groups(n);
         const int tpw = (ntile + nwg - 1) / nwg;
         const int ngrid = (ntile + tpw - 1) / tpw;
@@ -852,7 +893,7 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         double* red = work + (size_t)ngrid * stride;
         double* sink = red + stride;
         if (ev) (void)hipEventRecord(ev[0], st);
-        hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(256), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
+        hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(512), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
                            s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, sink, flag_log);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(fcg_reduce_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, ngrid, stride, rec,
