@@ -1,6 +1,9 @@
 // BOSP driver on one HIP stream (Algorithm "BOSP algorithm", Sections 3.2-3.3).
 //
-// Device data layout (column-major FP64, leading dimension n):
+// Device data layout (column-major FP64; the basis, locked and Step-6 blocks
+// use the padded leading dimension ldn = solver_ld(n), whose byte stride is
+// not a multiple of 2 KiB, so that the columns of a block do not all start on
+// the same HBM channel; the CG state uses n):
 //   buf[2] x {X, Y, KX, MY}   n x cap, cap = b + 4w + 1 columns.  The current
 //                             subspace U = [X~, P~, W~] (and V, K U, M V) sits
 //                             in one buffer at a column offset; the Ritz
@@ -68,10 +71,21 @@ struct HostStatus {
     unsigned long long napplies[2];
 };
 
+// leading dimension of the solver's n-row blocks: n rounded up to 32 doubles,
+// plus 32 more when that is a multiple of 256 (a power-of-two stride puts the
+// same row of every column on the same memory channel; measured 30% on the
+// Gram products at n = 2^18)
+int64_t solver_ld(int64_t n) {
+    int64_t ld = (n + 31) / 32 * 32;
+    if (ld % 256 == 0) ld += 32;
+    return ld;
+}
+
 struct Solver {
     Op* op;
     hipStream_t st;
     int64_t n;
+    int64_t ldn = 0;   // leading dimension of the blocks (solver_ld(n), set by buffers())
     int b, w, cap, nev, r0;
     double tol;
     lrep_solve_opts_t o{};
@@ -250,7 +264,9 @@ struct Solver {
     // allocates them, footprint() adds them up (the serving admission).
     template <class F>
     int buffers(F&& f) {
-        const size_t col = (size_t)n * sizeof(double);
+        // a caller-supplied product function gets contiguous blocks (ld n)
+        ldn = op->kind == 2 ? n : solver_ld(n);
+        const size_t col = (size_t)ldn * sizeof(double);
         for (int i = 0; i < 2; ++i) {
             CR(f(bX[i], col * cap));
             CR(f(bY[i], col * cap));
@@ -338,9 +354,9 @@ struct Solver {
         return s;
     }
 
-    int apply(int which, const double* X, int cols, double* Y, const int* flag = nullptr, hipEvent_t* ev = nullptr,
-              double* pq = nullptr) {
-        return op_apply(op, st, which, X, n, cols, Y, n, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev, pq);
+    int apply(int which, const double* X, int64_t ldx, int cols, double* Y, int64_t ldy, const int* flag = nullptr,
+              hipEvent_t* ev = nullptr, double* pq = nullptr) {
+        return op_apply(op, st, which, X, ldx, cols, Y, ldy, gwork.p, GEMM_WORK_ELEMS, Tlr, flag, ev, pq);
     }
 
     // the dense operator for the fused CG path (nullptr: use the generic apply)
@@ -365,11 +381,11 @@ struct Solver {
     }
 
     // fused CG on a low-rank operator (see fused_cg_kind)
-    int cg_fused(int kind, int which, const double* B, int nw, double cgtol, int maxit) {
+    int cg_fused(int kind, int which, const double* B, int64_t ldb, int nw, double cgtol, int maxit) {
         CgState s = cg_state(1, which);
         const double* Lr = kind == 2 ? op->Lr : nullptr;
         const int r = kind == 2 ? (int)op->rank : 0;
-        CK(fused_cg_init(st, (int)n, r, nw, op->delta, Lr, s, B, n, cgtol, gwork.p, GEMM_WORK_ELEMS));
+        CK(fused_cg_init(st, (int)n, r, nw, op->delta, Lr, s, B, ldb, cgtol, gwork.p, GEMM_WORK_ELEMS));
         for (int it = 0; it < maxit; ++it) {
             if (it > 0 && !capturing) {
                 const unsigned long long v = __atomic_load_n(note_h, __ATOMIC_ACQUIRE);
@@ -382,12 +398,14 @@ struct Solver {
         return LREP_OK;
     }
 
-    // solution of A x_j = rhs_j (which: 0 = K, 1 = M) into cgX; `maxit` CG steps
-    int cg(int which, const double* B, int nw, double cgtol, int maxit, bool host_check) {
+    // solution of A x_j = rhs_j (which: 0 = K, 1 = M; B with ld ldb) into cgX
+    // (ld n); `maxit` CG steps
+    int cg(int which, const double* B, int64_t ldb, int nw, double cgtol, int maxit, bool host_check) {
         // the long, tight-tolerance CG of the null-space set-up keeps the plain form
-        if (const int fk = host_check ? 0 : fused_cg_kind(which, nw)) return cg_fused(fk, which, B, nw, cgtol, maxit);
+        if (const int fk = host_check ? 0 : fused_cg_kind(which, nw))
+            return cg_fused(fk, which, B, ldb, nw, cgtol, maxit);
         CgState s = cg_state(1, which);
-        CK(cg_init(st, (int)n, nw, s, B, n, cgtol));
+        CK(cg_init(st, (int)n, nw, s, B, ldb, cgtol));
         const double* Ad = cg_stream_operator(which, nw);
         const int ntiles = (int)stream_tiles((int)n);
         // low-rank operators: the apply also returns p.q per 64-row tile
@@ -431,11 +449,11 @@ struct Solver {
                                          cg_any));
                 CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
             } else if (lr_pq) {
-                CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev, cg_pq));
+                CR(apply(which, cgP.p, n, nw, cgQ.p, n, cg_any, ev, cg_pq));
                 CK(cg_update_tiles(st, (int)n, nw, ntiles, cg_pq, s, cgtol));
                 CK(cg_direction(st, (int)n, nw, s));
             } else {
-                CR(apply(which, cgP.p, nw, cgQ.p, cg_any, ev));
+                CR(apply(which, cgP.p, n, nw, cgQ.p, n, cg_any, ev));
                 CK(lrep::cg_alpha(st, (int)n, nw, s));
                 CK(cg_update(st, (int)n, nw, s, cgtol));
                 CK(cg_direction(st, (int)n, nw, s));
@@ -484,39 +502,39 @@ struct Solver {
         return v;
     }
 
-    // Block MGS-Biorth of (X, Y) (n x m, ld n) into (oX, oY) (may alias X, Y).
-    int block_mgs(double* X, double* Y, int m, double* oX, double* oY, int* kept) {
+    // Block MGS-Biorth of (X, Y) (n x m, ld ldi) into (oX, oY) (ld ldo; may alias X, Y).
+    int block_mgs(double* X, double* Y, int64_t ldi, int m, double* oX, double* oY, int64_t ldo, int* kept) {
         *kept = 0;
         if (m == 0) return LREP_OK;
         const int64_t ldg = 2 * kMaxD;
         // pass 1
-        CR(gram(segs({{X, n, m}, {Y, n, m}}), segs({{X, n, m}, {Y, n, m}}), G, ldg, 0));
+        CR(gram(segs({{X, ldi, m}, {Y, ldi, m}}), segs({{X, ldi, m}, {Y, ldi, m}}), G, ldg, 0));
         CK(coef_mgs(st, m, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF, scr));
         CR(read_status());
         const int k1 = hs->status[ST_NKEPT];
         stats.mgs_drops += m - k1;
         if (k1 == 0) return LREP_OK;
-        CR(prod(segs({{X, n, m}}), Acoef, kMaxD, k1, tX.p, n, 1.0, 0.0));
-        CR(prod(segs({{Y, n, m}}), Bcoef, kMaxD, k1, tY.p, n, 1.0, 0.0));
+        CR(prod(segs({{X, ldi, m}}), Acoef, kMaxD, k1, tX.p, ldn, 1.0, 0.0));
+        CR(prod(segs({{Y, ldi, m}}), Bcoef, kMaxD, k1, tY.p, ldn, 1.0, 0.0));
         // pass 2
-        CR(gram(segs({{tX.p, n, k1}, {tY.p, n, k1}}), segs({{tX.p, n, k1}, {tY.p, n, k1}}), G, ldg, 0));
+        CR(gram(segs({{tX.p, ldn, k1}, {tY.p, ldn, k1}}), segs({{tX.p, ldn, k1}, {tY.p, ldn, k1}}), G, ldg, 0));
         CK(coef_mgs(st, k1, G, ldg, Acoef, Bcoef, status, MGS_COS_TOL, MGS_DEP_TOL_COEF, scr));
         CR(read_status());
         const int k2 = hs->status[ST_NKEPT];
         stats.mgs_drops += k1 - k2;
-        CR(prod(segs({{tX.p, n, k1}}), Acoef, kMaxD, k2, oX, n, 1.0, 0.0));
-        CR(prod(segs({{tY.p, n, k1}}), Bcoef, kMaxD, k2, oY, n, 1.0, 0.0));
+        CR(prod(segs({{tX.p, ldn, k1}}), Acoef, kMaxD, k2, oX, ldo, 1.0, 0.0));
+        CR(prod(segs({{tY.p, ldn, k1}}), Bcoef, kMaxD, k2, oY, ldo, 1.0, 0.0));
         *kept = k2;
         return LREP_OK;
     }
 
-    // U <- (I - X0 Y0^T) U, V <- (I - Y0 X0^T) V
+    // U <- (I - X0 Y0^T) U, V <- (I - Y0 X0^T) V (U, V with ld ldn; X0, Y0 ld n)
     int project_v0(double* U, double* V, int d) {
         if (r0 == 0 || d == 0) return LREP_OK;
-        CR(gram(segs({{op->Y0.p, n, r0}}), segs({{U, n, d}}), Cproj, kproj, 0));
-        CR(prod(segs({{op->X0.p, n, r0}}), Cproj, kproj, d, U, n, -1.0, 1.0));
-        CR(gram(segs({{op->X0.p, n, r0}}), segs({{V, n, d}}), Cproj, kproj, 0));
-        CR(prod(segs({{op->Y0.p, n, r0}}), Cproj, kproj, d, V, n, -1.0, 1.0));
+        CR(gram(segs({{op->Y0.p, n, r0}}), segs({{U, ldn, d}}), Cproj, kproj, 0));
+        CR(prod(segs({{op->X0.p, n, r0}}), Cproj, kproj, d, U, ldn, -1.0, 1.0));
+        CR(gram(segs({{op->X0.p, n, r0}}), segs({{V, ldn, d}}), Cproj, kproj, 0));
+        CR(prod(segs({{op->Y0.p, n, r0}}), Cproj, kproj, d, V, ldn, -1.0, 1.0));
         return LREP_OK;
     }
 
@@ -542,23 +560,23 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     double* V0 = bY[0].p;
     if (o.init_U) {
         if (o.init_on_device)
-            CK(hipMemcpy2DAsync(U0, n * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
+            CK(hipMemcpy2DAsync(U0, ldn * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
                                 d0, hipMemcpyDeviceToDevice, st));
         else
-            CK(hipMemcpy2DAsync(U0, n * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
+            CK(hipMemcpy2DAsync(U0, ldn * sizeof(double), o.init_U, o.ld_init * sizeof(double), n * sizeof(double),
                                 d0, hipMemcpyHostToDevice, st));
         // with a metric the start block is given in the original coordinates
         for (int c0 = 0; c0 < d0; c0 += kMaxD)
-            CR(op_metric_transform(op, st, true, std::min(kMaxD, d0 - c0), U0 + (size_t)c0 * n, n, tX.p, gwork.p,
+            CR(op_metric_transform(op, st, true, std::min(kMaxD, d0 - c0), U0 + (size_t)c0 * ldn, ldn, tX.p, gwork.p,
                                    GEMM_WORK_ELEMS));
     } else {
-        CK(philox_normal(st, (int)n, d0, o.seed, U0, n));
+        CK(philox_normal(st, (int)n, d0, o.seed, U0, ldn));
     }
-    CK(copy_cols(st, (int)n, d0, U0, n, V0, n));
+    CK(copy_cols(st, (int)n, d0, U0, ldn, V0, ldn));
     // Step 2
     CR(project_v0(U0, V0, d0));
     int kept = 0;
-    CR(block_mgs(U0, V0, d0, U0, V0, &kept));
+    CR(block_mgs(U0, V0, ldn, d0, U0, V0, ldn, &kept));
     d = kept;
     std::vector<double> lamc;
     int c = 0;
@@ -582,10 +600,10 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         if (d < 1) return fail(LREP_EBREAKDOWN, "subspace empty after MGS-Biorth");
         ++it;
         const int nxt = 1 - cur;
-        double* U = bX[cur].p + (size_t)off * n;
-        double* V = bY[cur].p + (size_t)off * n;
-        double* KU = bKX[cur].p + (size_t)off * n;
-        double* MV = bMY[cur].p + (size_t)off * n;
+        double* U = bX[cur].p + (size_t)off * ldn;
+        double* V = bY[cur].p + (size_t)off * ldn;
+        double* KU = bKX[cur].p + (size_t)off * ldn;
+        double* MV = bMY[cur].p + (size_t)off * ldn;
         double* NX = bX[nxt].p;
         double* NY = bY[nxt].p;
         double* NKX = bKX[nxt].p;
@@ -595,15 +613,15 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         mark(1);
         if (need_fresh || carried >= interval - 1) {
             if (carried > 0 && !need_fresh) {
-                CR(apply(0, U, d, tX.p));
-                CR(apply(1, V, d, tY.p));
-                CK(image_drift(st, (int)n, d, KU, tX.p, MV, tY.p, n, part, (size_t)256 * kMaxD * 4, offmax + 1));
-                CK(copy_cols(st, (int)n, d, tX.p, n, KU, n));
-                CK(copy_cols(st, (int)n, d, tY.p, n, MV, n));
+                CR(apply(0, U, ldn, d, tX.p, ldn));
+                CR(apply(1, V, ldn, d, tY.p, ldn));
+                CK(image_drift(st, (int)n, d, KU, tX.p, MV, tY.p, ldn, part, (size_t)256 * kMaxD * 4, offmax + 1));
+                CK(copy_cols(st, (int)n, d, tX.p, ldn, KU, ldn));
+                CK(copy_cols(st, (int)n, d, tY.p, ldn, MV, ldn));
                 drift_pending = true;
             } else {
-                CR(apply(0, U, d, KU));
-                CR(apply(1, V, d, MV));
+                CR(apply(0, U, ldn, d, KU, ldn));
+                CR(apply(1, V, ldn, d, MV, ldn));
             }
             stats.applies_K += d;
             stats.applies_M += d;
@@ -612,27 +630,27 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         } else {
             ++carried;
         }
-        CR(gram(segs({{U, n, d}}), segs({{KU, n, d}}), Kh, kMaxD, 1));
-        CR(gram(segs({{V, n, d}}), segs({{MV, n, d}}), Mh, kMaxD, 1));
-        CR(gram(segs({{U, n, d}}), segs({{V, n, d}}), S, kMaxD, 0));
+        CR(gram(segs({{U, ldn, d}}), segs({{KU, ldn, d}}), Kh, kMaxD, 1));
+        CR(gram(segs({{V, ldn, d}}), segs({{MV, ldn, d}}), Mh, kMaxD, 1));
+        CR(gram(segs({{U, ldn, d}}), segs({{V, ldn, d}}), S, kMaxD, 0));
         CK(max_offidentity(st, d, S, kMaxD, offmax));
         CK(small_lrep(st, d, Kh, Mh, kMaxD, lam, Xh, Yh, scr, status, gwork.p, GEMM_WORK_ELEMS));
         const int nr = std::min(b, d);
         auto pull = [&](int g0, int g1, int col0) -> int {
             if (g1 <= g0) return LREP_OK;
             const int k = g1 - g0;
-            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+            const Seg A4[4] = {{U, ldn, d}, {V, ldn, d}, {KU, ldn, d}, {MV, ldn, d}};
             const double* B4[4] = {Xh + (size_t)g0 * kMaxD, Yh + (size_t)g0 * kMaxD, Xh + (size_t)g0 * kMaxD,
                                    Yh + (size_t)g0 * kMaxD};
-            double* C4[4] = {NX + (size_t)col0 * n, NY + (size_t)col0 * n, NKX + (size_t)col0 * n,
-                             NMY + (size_t)col0 * n};
-            CK(gemm_nn_batch(st, (int)n, k, d, 4, A4, B4, kMaxD, C4, n, 1.0, 0.0));
+            double* C4[4] = {NX + (size_t)col0 * ldn, NY + (size_t)col0 * ldn, NKX + (size_t)col0 * ldn,
+                             NMY + (size_t)col0 * ldn};
+            CK(gemm_nn_batch(st, (int)n, k, d, 4, A4, B4, kMaxD, C4, ldn, 1.0, 0.0));
             return LREP_OK;
         };
         CR(pull(0, nr, 0));
         // Step 4
         mark(2);
-        CK(residual_eps(st, (int)n, nr, NX, NY, NKX, NMY, n, lam, eps, part, (size_t)256 * kMaxD * 4, tickets));
+        CK(residual_eps(st, (int)n, nr, NX, NY, NKX, NMY, ldn, lam, eps, part, (size_t)256 * kMaxD * 4, tickets));
         CK(hipMemcpyAsync(hs->eps, eps, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
         CK(hipMemcpyAsync(hs->lam, lam, sizeof(double) * d, hipMemcpyDeviceToHost, st));
         CK(hipMemcpyAsync(&hs->offmax, offmax, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -670,16 +688,16 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
                 // written to the other buffer set (free until the pull-back of
                 // the redone iteration)
                 CK(biorth_fix_coef(st, d, S, kMaxD, Acoef, Bcoef, kMaxD));
-                const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+                const Seg A4[4] = {{U, ldn, d}, {V, ldn, d}, {KU, ldn, d}, {MV, ldn, d}};
                 const double* B4[4] = {Acoef, Bcoef, Acoef, Bcoef};
                 double* C4[4] = {NX, NY, NKX, NMY};
-                CK(gemm_nn_batch(st, (int)n, d, d, 4, A4, B4, kMaxD, C4, n, 1.0, 0.0));
+                CK(gemm_nn_batch(st, (int)n, d, d, 4, A4, B4, kMaxD, C4, ldn, 1.0, 0.0));
                 cur = nxt;
                 off = 0;
                 continue;
             }
             need_fresh = true;
-            CR(block_mgs(U, V, d, U, V, &kept));
+            CR(block_mgs(U, V, ldn, d, U, V, ldn, &kept));
             d = kept;
             continue;
         }
@@ -698,8 +716,8 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         }
         if (p >= need) {
             // converged: X = [Xc, X~(:, 0:need)]
-            CK(copy_cols(st, (int)n, need, NX, n, Xc.p + (size_t)c * n, n));
-            CK(copy_cols(st, (int)n, need, NY, n, Yc.p + (size_t)c * n, n));
+            CK(copy_cols(st, (int)n, need, NX, ldn, Xc.p + (size_t)c * ldn, ldn));
+            CK(copy_cols(st, (int)n, need, NY, ldn, Yc.p + (size_t)c * ldn, ldn));
             for (int g = 0; g < need; ++g) {
                 lamc.push_back(hs->lam[g]);
                 epsc.push_back(hs->eps[g]);
@@ -710,8 +728,8 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         }
         int L = (p >= lock_unit && d > lock_unit) ? lock_unit : 0;
         if (L) {
-            CK(copy_cols(st, (int)n, L, NX, n, Xc.p + (size_t)c * n, n));
-            CK(copy_cols(st, (int)n, L, NY, n, Yc.p + (size_t)c * n, n));
+            CK(copy_cols(st, (int)n, L, NX, ldn, Xc.p + (size_t)c * ldn, ldn));
+            CK(copy_cols(st, (int)n, L, NY, ldn, Yc.p + (size_t)c * ldn, ldn));
             for (int g = 0; g < L; ++g) {
                 lamc.push_back(hs->lam[g]);
                 epsc.push_back(hs->eps[g]);
@@ -763,12 +781,12 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         mark(4);
         auto step6 = [&]() -> int {
             for (int j = 0; j < o.ngs; ++j) {
-                CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, n, NX, NMY, n, wincol, lamw, rhs.p, n));
-                CR(cg(1, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
-                CK(copy_cols(st, (int)n, nw, cgX.p, n, Zs.p, n));
-                CK(gs_rhs(st, (int)n, nw, Zs.p, n, NY, NKX, n, wincol, lamw, rhs.p, n));
-                CR(cg(0, rhs.p, nw, o.cg_tol, o.cg_maxit, false));
-                CK(copy_cols(st, (int)n, nw, cgX.p, n, Ws.p, n));
+                CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, ldn, NX, NMY, ldn, wincol, lamw, rhs.p, ldn));
+                CR(cg(1, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit, false));
+                CK(copy_cols(st, (int)n, nw, cgX.p, n, Zs.p, ldn));
+                CK(gs_rhs(st, (int)n, nw, Zs.p, ldn, NY, NKX, ldn, wincol, lamw, rhs.p, ldn));
+                CR(cg(0, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit, false));
+                CK(copy_cols(st, (int)n, nw, cgX.p, n, Ws.p, ldn));
             }
             return LREP_OK;
         };
@@ -802,35 +820,35 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         CK(hipEventSynchronize(np_ev));
         const int np = hs->status[ST_NP];
         stats.mgs_drops += nw - np;
-        double* Pt = NX + (size_t)hi * n;
-        double* Qt = NY + (size_t)hi * n;
+        double* Pt = NX + (size_t)hi * ldn;
+        double* Qt = NY + (size_t)hi * ldn;
         // the next subspace's images are carried whenever carrying is on, also
         // into a refresh, where they are compared with the fresh ones
         const bool carry_next = interval > 1;
         {
             // P~ = U P^, Q~ = V Q^ (Step 5), into columns [hi, hi + np) of the next basis
-            const Seg A4[4] = {{U, n, d}, {V, n, d}, {KU, n, d}, {MV, n, d}};
+            const Seg A4[4] = {{U, ldn, d}, {V, ldn, d}, {KU, ldn, d}, {MV, ldn, d}};
             const double* B4[4] = {Ph, Qh, Ph, Qh};
-            double* C4[4] = {Pt, Qt, NKX + (size_t)hi * n, NMY + (size_t)hi * n};
-            CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, n, 1.0, 0.0));
+            double* C4[4] = {Pt, Qt, NKX + (size_t)hi * ldn, NMY + (size_t)hi * ldn};
+            CK(gemm_nn_batch(st, (int)n, np, d, carry_next ? 4 : 2, A4, B4, kMaxD, C4, ldn, 1.0, 0.0));
         }
         // projection against [X0, Xc, X~_active, P~], applied twice
         const int kact = na + np;
-        auto Xall = segs({{op->X0.p, n, (int)r0}, {Xc.p, n, c}, {NX + (size_t)L * n, n, kact}});
-        auto Yall = segs({{op->Y0.p, n, (int)r0}, {Yc.p, n, c}, {NY + (size_t)L * n, n, kact}});
+        auto Xall = segs({{op->X0.p, n, (int)r0}, {Xc.p, ldn, c}, {NX + (size_t)L * ldn, ldn, kact}});
+        auto Yall = segs({{op->Y0.p, n, (int)r0}, {Yc.p, ldn, c}, {NY + (size_t)L * ldn, ldn, kact}});
         for (int pass = 0; pass < 2; ++pass) {
-            CR(gram(Yall, segs({{Ws.p, n, nw}}), Cproj, kproj, 0));
-            CR(prod(Xall, Cproj, kproj, nw, Ws.p, n, -1.0, 1.0));
-            CR(gram(Xall, segs({{Zs.p, n, nw}}), Cproj, kproj, 0));
-            CR(prod(Yall, Cproj, kproj, nw, Zs.p, n, -1.0, 1.0));
+            CR(gram(Yall, segs({{Ws.p, ldn, nw}}), Cproj, kproj, 0));
+            CR(prod(Xall, Cproj, kproj, nw, Ws.p, ldn, -1.0, 1.0));
+            CR(gram(Xall, segs({{Zs.p, ldn, nw}}), Cproj, kproj, 0));
+            CR(prod(Yall, Cproj, kproj, nw, Zs.p, ldn, -1.0, 1.0));
         }
         // MGS-Biorth of (W~, Z~), appended after P~
         int nwk = 0;
-        CR(block_mgs(Ws.p, Zs.p, nw, NX + (size_t)(hi + np) * n, NY + (size_t)(hi + np) * n, &nwk));
+        CR(block_mgs(Ws.p, Zs.p, ldn, nw, NX + (size_t)(hi + np) * ldn, NY + (size_t)(hi + np) * ldn, ldn, &nwk));
         if (carry_next && nwk > 0) {
-            const size_t o2 = (size_t)(hi + np) * n;
-            CR(apply(0, NX + o2, nwk, NKX + o2));
-            CR(apply(1, NY + o2, nwk, NMY + o2));
+            const size_t o2 = (size_t)(hi + np) * ldn;
+            CR(apply(0, NX + o2, ldn, nwk, NKX + o2, ldn));
+            CR(apply(1, NY + o2, ldn, nwk, NMY + o2, ldn));
             stats.applies_K += nwk;
             stats.applies_M += nwk;
         }
@@ -859,21 +877,21 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
     // the bases they were locked from, amplified by the pull-back coefficients.
     // One more projection, a no-op for exact eigenvectors, restores it.
     for (int c0 = 0; c0 < c && r0 > 0; c0 += kMaxD)
-        CR(project_v0(Xc.p + (size_t)c0 * n, Yc.p + (size_t)c0 * n, std::min(kMaxD, c - c0)));
+        CR(project_v0(Xc.p + (size_t)c0 * ldn, Yc.p + (size_t)c0 * ldn, std::min(kMaxD, c - c0)));
     if (c > 0 && c <= kMaxD) {
         // The returned pairs were locked from bases biorthogonal to the
         // restore threshold; a first-order correction brings X^T Y = I to
         // rounding level (each vector moves by O(|X^T Y - I|), far below the
         // residual tolerance).
         const int64_t ldg = 2 * kMaxD;
-        CR(gram(segs({{Xc.p, n, c}}), segs({{Yc.p, n, c}}), G, ldg, 0));
+        CR(gram(segs({{Xc.p, ldn, c}}), segs({{Yc.p, ldn, c}}), G, ldg, 0));
         CK(biorth_fix_coef(st, c, G, ldg, Acoef, Bcoef, kMaxD));
-        const Seg A2[2] = {{Xc.p, n, c}, {Yc.p, n, c}};
+        const Seg A2[2] = {{Xc.p, ldn, c}, {Yc.p, ldn, c}};
         const double* B2[2] = {Acoef, Bcoef};
         double* C2[2] = {tX.p, tY.p};
-        CK(gemm_nn_batch(st, (int)n, c, c, 2, A2, B2, kMaxD, C2, n, 1.0, 0.0));
-        CK(copy_cols(st, (int)n, c, tX.p, n, Xc.p, n));
-        CK(copy_cols(st, (int)n, c, tY.p, n, Yc.p, n));
+        CK(gemm_nn_batch(st, (int)n, c, c, 2, A2, B2, kMaxD, C2, ldn, 1.0, 0.0));
+        CK(copy_cols(st, (int)n, c, tX.p, ldn, Xc.p, ldn));
+        CK(copy_cols(st, (int)n, c, tY.p, ldn, Yc.p, ldn));
     }
     if (c > 0) {
         double* OX = op->null_on_M() ? Yc.p : Xc.p;
@@ -881,13 +899,13 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         // with a metric B = C C^T, back to the original coordinates: x = C^-T x^, y = C^-T y^
         for (int c0 = 0; c0 < c && op->has_metric(); c0 += kMaxD) {
             const int cc = std::min(kMaxD, c - c0);
-            CR(op_metric_transform(op, st, false, cc, OX + (size_t)c0 * n, n, tX.p, gwork.p, GEMM_WORK_ELEMS));
-            CR(op_metric_transform(op, st, false, cc, OY + (size_t)c0 * n, n, tX.p, gwork.p, GEMM_WORK_ELEMS));
+            CR(op_metric_transform(op, st, false, cc, OX + (size_t)c0 * ldn, ldn, tX.p, gwork.p, GEMM_WORK_ELEMS));
+            CR(op_metric_transform(op, st, false, cc, OY + (size_t)c0 * ldn, ldn, tX.p, gwork.p, GEMM_WORK_ELEMS));
         }
-        CK(sign_normalise(st, (int)n, c, OX, OY, n));
+        CK(sign_normalise(st, (int)n, c, OX, OY, ldn));
         const hipMemcpyKind kind = o.result_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        CK(hipMemcpy2DAsync(X_out, ldxy * sizeof(double), OX, n * sizeof(double), n * sizeof(double), c, kind, st));
-        CK(hipMemcpy2DAsync(Y_out, ldxy * sizeof(double), OY, n * sizeof(double), n * sizeof(double), c, kind, st));
+        CK(hipMemcpy2DAsync(X_out, ldxy * sizeof(double), OX, ldn * sizeof(double), n * sizeof(double), c, kind, st));
+        CK(hipMemcpy2DAsync(Y_out, ldxy * sizeof(double), OY, ldn * sizeof(double), n * sizeof(double), c, kind, st));
         CK(hipMemcpyAsync(lambda_out, lamc.data(), sizeof(double) * c,
                           o.result_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
         CK(hipStreamSynchronize(st));
@@ -1087,10 +1105,10 @@ int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t) {
     if (rc == LREP_OK) rc = op->Y0.alloc(c, (size_t)op->n * r * sizeof(double));
     if (rc != LREP_OK) return rc;
     const int maxit = (int)std::min<int64_t>(20 * op->n + 100, 200000);
-    rc = s.cg(1, X0t, (int)r, 1e-14, maxit, true);
+    rc = s.cg(1, X0t, op->n, (int)r, 1e-14, maxit, true);
     if (rc != LREP_OK) return rc;
     int kept = 0;
-    rc = s.block_mgs(const_cast<double*>(X0t), s.cgX.p, (int)r, op->X0.p, op->Y0.p, &kept);
+    rc = s.block_mgs(const_cast<double*>(X0t), s.cgX.p, op->n, (int)r, op->X0.p, op->Y0.p, op->n, &kept);
     if (rc != LREP_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return LREP_EDEVICE;
     if (kept != r) return LREP_ENOTSPD;
@@ -1139,7 +1157,7 @@ int find_nullspace(Op* op, hipStream_t st, int64_t rmax, double tol, uint64_t se
         return LREP_OK;
     };
     CK(philox_normal(st, n, m, seed, X0, n));
-    CR(s.apply(0, X0, m, Bv));
+    CR(s.apply(0, X0, n, m, Bv, n));
     std::vector<double> nx, nb, nz, nr;
     CR(sqnorms(X0, m, nx));
     CR(sqnorms(Bv, m, nb));
@@ -1150,7 +1168,7 @@ int find_nullspace(Op* op, hipStream_t st, int64_t rmax, double tol, uint64_t se
         return LREP_ENUMERIC;
     }
     const int maxit = (int)std::min<int64_t>(20 * (int64_t)n + 100, 200000);
-    CR(s.cg(0, Bv, m, 1e-15, maxit, true));
+    CR(s.cg(0, Bv, n, m, 1e-15, maxit, true));
     CK(sub_cols(st, n, m, X0, n, s.cgX.p, n, Z, n));
     CR(sqnorms(Z, m, nz));
     // a projection at rounding level carries no null direction (A definite on it)
@@ -1165,10 +1183,10 @@ int find_nullspace(Op* op, hipStream_t st, int64_t rmax, double tol, uint64_t se
     if (k == 0) return LREP_OK;
     CK(copy_cols(st, n, k, Bv, n, X0, n));
     int kept = 0;
-    CR(s.block_mgs(Bv, X0, k, Bv, X0, &kept));
+    CR(s.block_mgs(Bv, X0, n, k, Bv, X0, n, &kept));
     if (kept == 0) return LREP_OK;
     // the orthonormal basis must satisfy ||A z|| <= tol ||A||
-    CR(s.apply(0, Bv, kept, Z));
+    CR(s.apply(0, Bv, n, kept, Z, n));
     CR(sqnorms(Z, kept, nr));
     double worst = 0.0;
     for (int j = 0; j < kept; ++j) worst = std::max(worst, std::sqrt(nr[j]) / normest);
@@ -1207,7 +1225,7 @@ int block_mgs_standalone(Ctx* c, hipStream_t st, int64_t n, int m, double* X, do
     s.r0 = 0;
     if (m < 0 || m > kMaxD) return LREP_EINVAL;
     int rc = s.alloc();
-    if (rc == LREP_OK) rc = s.block_mgs(X, Y, m, X, Y, kept);
+    if (rc == LREP_OK) rc = s.block_mgs(X, Y, n, m, X, Y, n, kept);
     if (rc == LREP_OK && hipStreamSynchronize(st) != hipSuccess) rc = LREP_EDEVICE;
     return rc;
 }
@@ -1230,7 +1248,7 @@ int cg_standalone(Op* op, hipStream_t st, int which, int nw, const double* B, do
     s.o.fused_cg = fused;
     if (nw < 1 || nw > 32 || maxit < 1 || !(tol > 0)) return LREP_EINVAL;
     int rc = s.alloc();
-    if (rc == LREP_OK) rc = s.cg(which, B, nw, tol, maxit, false);
+    if (rc == LREP_OK) rc = s.cg(which, B, op->n, nw, tol, maxit, false);
     if (rc == LREP_OK && hipMemcpy2DAsync(X, op->n * sizeof(double), s.cgX.p, op->n * sizeof(double),
                                           op->n * sizeof(double), nw, hipMemcpyDeviceToDevice, st) != hipSuccess)
         rc = LREP_EDEVICE;
