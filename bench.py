@@ -60,6 +60,11 @@ WORKLOADS = {
                           precision=1),
     "dense8192fp16": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                           precision=2),
+    # BF16x3: operator and CG block split into hi/mid/lo BF16 parts, FP32-accurate CG products
+    "dense32768bf16x3": dict(kind="dense", n=32768, seed=1004, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                             precision=3, cpu_iters=4),
+    "dense8192bf16x3": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
+                            precision=3),
     # one oracle iteration takes about a minute on the host: the baseline is a bounded sample
     "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8,
                          cpu_iters=1),
@@ -295,7 +300,8 @@ def serve(args, np, torch, gen, L):
 def describe(w):
     if w["kind"] == "dense":
         z = f", {w['zeros']} exact zeros in m" if w["zeros"] else ""
-        z += {0: "", 1: "; CG applies in BF16 (f32 accumulate)", 2: "; CG applies in FP16 (f32 accumulate)"}[
+        z += {0: "", 1: "; CG applies in BF16 (f32 accumulate)", 2: "; CG applies in FP16 (f32 accumulate)",
+              3: "; CG applies in BF16x3 (hi/mid/lo BF16 parts, six part products, f32 accumulate)"}[
             w.get("precision", 0)]
         if w.get("metric_dense"):
             z += ("; generalized LREP K x = lambda B y, M y = lambda B x, dense B = Q diag(beta) Q^T, Q Haar, "
@@ -491,7 +497,10 @@ def main():
     roofline = None
     if achieved is not None:
         traffic = measured_traffic(args.workload)
-        if w["kind"] == "dense" and w.get("precision", 0):
+        if w["kind"] == "dense" and w.get("precision", 0) == 3:
+            kname = "apply16x3_stream_kernel (BF16x3 CG block apply: three BF16 operator parts, w=%d)" % window
+            abytes = 6.0 * n * n + 14.0 * n * window
+        elif w["kind"] == "dense" and w.get("precision", 0):
             kname = "apply16_stream_kernel (16-bit CG block apply, w=%d)" % window
             abytes = 2.0 * n * n + 10.0 * n * window
         elif w["kind"] == "dense":
@@ -565,7 +574,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(total * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": {0: "f64", 1: "bf16 CG applies (f32 accumulate), f64 elsewhere",
-                  2: "f16 CG applies (f32 accumulate), f64 elsewhere"}[w.get("precision", 0)],
+                  2: "f16 CG applies (f32 accumulate), f64 elsewhere",
+                  3: "bf16x3 CG applies (f32 accumulate), f64 elsewhere"}[w.get("precision", 0)],
         "data": "synthetic",
         "config": {"workload": describe(w), "n": n, "nev": nev, "block": block, "window": window, "tol": tol,
                    "seed": w["seed"], "parallelism": "single GPU"},

@@ -88,12 +88,16 @@ typedef struct lrep_solve_opts {
                                  1: the CG applies of Step 6 use a BF16 copy of K and
                                  M and a BF16 copy of the CG block, FP32 accumulation
                                  (MFMA), FP64 result; 2: the same in FP16 with each CG
-                                 column scaled by a power of two.  Everything else
-                                 (Rayleigh-Ritz images, residuals, MGS-Biorth, small
-                                 problem) stays FP64.  The 16-bit copies (2 n^2 bytes
-                                 each, charged to the context budget) are made at the
-                                 first such solve and kept with the operator; n must
-                                 be a multiple of 8.                                  */
+                                 column scaled by a power of two; 3: BF16x3, the
+                                 operator and the CG block each split into three
+                                 BF16 parts (hi, mid, lo) and the six part products
+                                 of order <= 2 summed in FP32 (an FP32-accurate
+                                 product).  Everything else (Rayleigh-Ritz images,
+                                 residuals, MGS-Biorth, small problem) stays FP64.
+                                 The 16-bit copies (2 n^2 bytes each, 6 n^2 for
+                                 BF16x3, charged to the context budget) are made at
+                                 the first such solve and kept with the operator; n
+                                 must be a multiple of 8.                             */
     int32_t profile;          /* 1: time every Step-6 operator apply with HIP events on
                                  the solve's stream (results in lrep_stats_t.prof_*)  */
     double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this

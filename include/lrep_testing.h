@@ -48,15 +48,18 @@ int lrep_test_cg(lrep_op_t op, int which, int nw, const double* B, double* X, do
                  int64_t* applies);
 
 /* out (n x n, ld n, 16-bit) = the BF16 (precision 1) or FP16 (precision 2)
- * copy of 0.5 (A + A^T) that the mixed-precision CG applies use: each
- * value rounded to FP32, then to 16 bits, both to nearest even.  A is a
- * device FP64 matrix (ld lda), out a device array of n * n 16-bit values. */
+ * copy of 0.5 (A + A^T) that the mixed-precision CG applies use: each value
+ * rounded once, to nearest even, from FP64 to 16 bits.  Precision 3 (BF16x3):
+ * three such matrices, the hi, mid and lo BF16 parts (each the rounding of
+ * what the earlier parts leave), at out, out + n^2, out + 2 n^2.  A is a
+ * device FP64 matrix (ld lda), out a device array of n * n 16-bit values
+ * (3 n * n for precision 3). */
 int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, int64_t lda, uint16_t* out);
 
 /* Y = A16 X through the mixed-precision CG apply: A16 a 16-bit copy made as
  * above, X scaled column by column by a power of two from rr[j] = |x_j|^2
- * before its conversion when precision is 2 (FP16), FP32 accumulation, FP64
- * result.  X, rr and Y are device arrays, X and Y n x cols (ld n),
+ * before its conversion when precision is 2 (FP16), X split in three BF16
+ * parts when precision is 3, FP32 accumulation, FP64 result.  X, rr and Y are device arrays, X and Y n x cols (ld n),
  * cols <= 32; n a multiple of 8, n >= 64. */
 int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint16_t* A16, const double* X,
                       const double* rr, double* Y);

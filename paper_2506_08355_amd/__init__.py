@@ -473,12 +473,14 @@ def lrep_test_apply(op, which, X, Y):
 
 
 def lrep_test_convert16(ctx, precision, A, out):
-    """out (n * n 16-bit device tensor, column-major n x n) = the 16-bit copy
-    of the column-major FP64 device matrix A."""
+    """out (n * n 16-bit device tensor, column-major n x n; 3 n * n, the hi,
+    mid and lo parts, for precision 3) = the 16-bit copy of the column-major
+    FP64 device matrix A."""
     p, ld, _ = colmajor(A)
     n = A.shape[0]
-    if out.numel() != n * n or out.element_size() != 2:
-        raise ValueError("out must hold n * n 16-bit values")
+    parts = 3 if precision == 3 else 1
+    if out.numel() != parts * n * n or out.element_size() != 2:
+        raise ValueError("out must hold %d n * n 16-bit values" % parts)
     _ready(out)
     return _check(lib().lrep_test_convert16(ctx, precision, n, p, ld, ctypes.c_void_p(out.data_ptr())), ctx,
                   "lrep_test_convert16")
@@ -488,8 +490,9 @@ def lrep_test_apply16(ctx, precision, A16, X, rr, Y):
     """Y = A16 X on a 16-bit copy (X, Y column-major device n x cols, rr the
     device vector of squared column norms of X)."""
     n, cols = X.shape
-    if A16.numel() != n * n or A16.element_size() != 2:
-        raise ValueError("A16 must hold n * n 16-bit values")
+    parts = 3 if precision == 3 else 1
+    if A16.numel() != parts * n * n or A16.element_size() != 2:
+        raise ValueError("A16 must hold %d n * n 16-bit values" % parts)
     _ready(A16)
     return _check(lib().lrep_test_apply16(ctx, precision, n, cols, ctypes.c_void_p(A16.data_ptr()),
                                           colmajor(X)[0], ctypes.c_void_p(rr.data_ptr()), colmajor(Y)[0]),

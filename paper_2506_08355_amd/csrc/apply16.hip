@@ -20,6 +20,13 @@
 // two 2^e_j ~ sqrt(n / |r_j|^2) before the conversion (elements of size
 // about 1) and the product is scaled back exactly.  BF16 keeps FP32's range
 // and needs no scaling.
+//
+// BF16x3 (precision 3): the operator and the block are each split into three
+// BF16 parts, v = hi + mid + lo, every part the rounding of what the earlier
+// ones leave (so hi + mid + lo carries 24 significant bits, FP32's), and the
+// product sums the six part products of total order <= 2 (hi hi, hi mid,
+// mid hi, hi lo, lo hi, mid mid) in FP32: an FP32-accurate product from BF16
+// MFMAs, reading 6 n^2 bytes of operator (FP64: 8 n^2).
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -40,11 +47,22 @@ constexpr int PF = 2;    // k-steps per prefetch half
 // (no intermediate FP32 rounding)
 template <int P>
 __device__ __forceinline__ u16 to16(double v) {
-    if constexpr (P == 1) return __builtin_bit_cast(u16, (__bf16)v);
+    if constexpr (P == 1 || P == 3) return __builtin_bit_cast(u16, (__bf16)v);
     else return __builtin_bit_cast(u16, (_Float16)v);
 }
+// the three BF16 parts of v (each the rounding of the remainder, FP64 arithmetic)
+__device__ __forceinline__ void split3(double v, u16& hi, u16& mid, u16& lo) {
+    const __bf16 h = (__bf16)v;
+    const double r1 = v - (double)h;
+    const __bf16 m = (__bf16)r1;
+    const double r2 = r1 - (double)m;
+    hi = __builtin_bit_cast(u16, h);
+    mid = __builtin_bit_cast(u16, m);
+    lo = __builtin_bit_cast(u16, (__bf16)r2);
+}
 
-// out (16-bit, n x n, ld n) = 0.5 (A + A^T) rounded; 32 x 32 tiles through LDS
+// out (16-bit, n x n, ld n) = 0.5 (A + A^T) rounded; 32 x 32 tiles through LDS.
+// P = 3: three such matrices, hi, mid, lo parts, at out, out + n^2, out + 2 n^2.
 template <int P>
 __global__ __launch_bounds__(256) void convert16_kernel(int n, const double* __restrict__ A, int64_t lda,
                                                         u16* __restrict__ out) {
@@ -62,14 +80,24 @@ __global__ __launch_bounds__(256) void convert16_kernel(int n, const double* __r
         if (i < n && j < n) {
             const double a = A[(int64_t)j * lda + i];
             const double b = t[r][tx];          // A(j, i)
-            out[(int64_t)j * n + i] = to16<P>(0.5 * (a + b));
+            if constexpr (P == 3) {
+                const size_t nn = (size_t)n * n;
+                u16 h, m, l;
+                split3(0.5 * (a + b), h, m, l);
+                out[(int64_t)j * n + i] = h;
+                out[nn + (int64_t)j * n + i] = m;
+                out[2 * nn + (int64_t)j * n + i] = l;
+            } else {
+                out[(int64_t)j * n + i] = to16<P>(0.5 * (a + b));
+            }
         }
     }
 }
 
 // CG direction (p = r + beta p on the active columns unless `first`) and the
 // 16-bit block Xh (n x 32, column-major, zero-padded), column j scaled by
-// 2^e_j (FP16) where e_j = round(log2(sqrt(n / rr_j))).
+// 2^e_j (FP16) where e_j = round(log2(sqrt(n / rr_j))); P = 3: the hi, mid,
+// lo parts at Xh, Xh + 32 n, Xh + 64 n.
 template <int P>
 __global__ __launch_bounds__(256) void cg_dir_pack16_kernel(int n, int w, double* __restrict__ Pm,
                                                             const double* __restrict__ R,
@@ -93,13 +121,21 @@ __global__ __launch_bounds__(256) void cg_dir_pack16_kernel(int n, int w, double
                 Pm[(int64_t)c * n + i] = v;
             }
         }
-        Xh[(int64_t)c * n + i] = to16<P>(v * sc);
+        if constexpr (P == 3) {
+            u16 h, m, l;
+            split3(v, h, m, l);
+            Xh[(int64_t)c * n + i] = h;
+            Xh[(int64_t)(32 + c) * n + i] = m;
+            Xh[(int64_t)(64 + c) * n + i] = l;
+        } else {
+            Xh[(int64_t)c * n + i] = to16<P>(v * sc);
+        }
     }
 }
 
 template <int P>
 __device__ __forceinline__ f4 mfma16(uint4 a, uint4 b, f4 c) {
-    if constexpr (P == 1)
+    if constexpr (P == 1 || P == 3)
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
                                                       c, 0, 0, 0);
     else
@@ -190,6 +226,86 @@ __global__ __launch_bounds__(64) void apply16_stream_kernel(int n, const u16* __
         for (int u = 0; u < 2; ++u) *reinterpret_cast<f4*>(out + (f * 2 + u) * 4) = acc[f][u];
 }
 
+// The BF16x3 form of apply16_stream_kernel: the operator's hi, mid, lo parts
+// at A, A + n^2, A + 2 n^2 and the block's at X, X + 32 n, X + 64 n; per
+// k-step the six part products of order <= 2 into the one FP32 accumulator
+// (smallest first).  One k-step per prefetch half (the parts triple the
+// registers a step holds).
+__global__ __launch_bounds__(64) void apply16x3_stream_kernel(int n, const u16* __restrict__ A,
+                                                              const u16* __restrict__ X, int kchunk,
+                                                              float* __restrict__ part,
+                                                              const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    const int lane = threadIdx.x, tile = blockIdx.x, split = blockIdx.y;
+    const int row0 = tile * WR;
+    const int k_begin = split * kchunk;
+    const int k_end = min(n, k_begin + kchunk);
+    const int nfull = max(0, (k_end - k_begin) / KS);
+    const int r = lane % 16, g = lane / 16;
+    const int64_t nn = (int64_t)n * n, xn = (int64_t)32 * n;
+    f4 acc[4][2];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[f][0] = acc[f][1] = f4{0.f, 0.f, 0.f, 0.f};
+    // rows beyond n read row n - 1 (valid memory) and are dropped by the reduction
+    const u16* ap[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) ap[f] = A + (int64_t)min(row0 + 16 * f + r, n - 1) * n + k_begin + 8 * g;
+    const u16* bp0 = X + (int64_t)r * n + k_begin + 8 * g;
+    const u16* bp1 = X + (int64_t)(16 + r) * n + k_begin + 8 * g;
+    // a[part][f], b[part][u] of one k-step (part 0 hi, 1 mid, 2 lo)
+    auto load = [&](uint4 (&a)[3][4], uint4 (&b)[3][2], int s, bool in) {
+        const int64_t o = (int64_t)s * KS;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (in) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) a[q][f] = *reinterpret_cast<const uint4*>(ap[f] + q * nn + o);
+                b[q][0] = *reinterpret_cast<const uint4*>(bp0 + q * xn + o);
+                b[q][1] = *reinterpret_cast<const uint4*>(bp1 + q * xn + o);
+            } else {
+                const uint4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int f = 0; f < 4; ++f) a[q][f] = z;
+                b[q][0] = b[q][1] = z;
+            }
+        }
+    };
+    auto compute = [&](const uint4 (&a)[3][4], const uint4 (&b)[3][2]) {
+        // (operator part, block part): lo hi, hi lo, mid mid, mid hi, hi mid, hi hi
+        constexpr int pa[6] = {2, 0, 1, 1, 0, 0}, pb[6] = {0, 2, 1, 0, 1, 0};
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                acc[f][0] = mfma16<3>(a[pa[t]][f], b[pb[t]][0], acc[f][0]);
+                acc[f][1] = mfma16<3>(a[pa[t]][f], b[pb[t]][1], acc[f][1]);
+            }
+    };
+    if (nfull > 0) {
+        uint4 a0[3][4], b0[3][2], a1[3][4], b1[3][2];
+        load(a0, b0, 0, true);
+        for (int s = 0; s < nfull; s += 2) {
+            load(a1, b1, min(s + 1, nfull - 1), true);
+            compute(a0, b0);
+            load(a0, b0, min(s + 2, nfull - 1), true);
+            if (s + 1 < nfull) compute(a1, b1);
+        }
+    }
+    if (k_begin + KS * nfull < k_end) {
+        // last partial k-step: a lane's 8 values are all in range or all out (n % 8 == 0)
+        const bool kin = k_begin + (int64_t)nfull * KS + 8 * g < k_end;
+        uint4 aa[3][4], bb[3][2];
+        load(aa, bb, nfull, kin);
+        compute(aa, bb);
+    }
+    const int ntiles = (n + WR - 1) / WR;
+    float* out = part + (((int64_t)split * ntiles + tile) * WAVE + lane) * 32;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) *reinterpret_cast<f4*>(out + (f * 2 + u) * 4) = acc[f][u];
+}
+
 // Q (FP64, n x w, ld n) = 2^-e_j * sum_split part, fixed split order, and
 // pq[tile * 32 + j] = sum over the tile's rows of P[:, j] Q[:, j].  Block
 // (tile, col group) of 256 threads: thread = (row, column pair).
@@ -240,6 +356,8 @@ hipError_t convert_operator16(hipStream_t st, int precision, int n, const double
         hipLaunchKernelGGL(convert16_kernel<1>, grid, dim3(256), 0, st, n, A, lda, out);
     else if (precision == 2)
         hipLaunchKernelGGL(convert16_kernel<2>, grid, dim3(256), 0, st, n, A, lda, out);
+    else if (precision == 3)
+        hipLaunchKernelGGL(convert16_kernel<3>, grid, dim3(256), 0, st, n, A, lda, out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -249,7 +367,7 @@ hipError_t cg_dense_apply16(hipStream_t st, int precision, int n, int w, const u
                             const double* R, const double* beta, const int* active, const double* rr, int first,
                             double* Q, double* pq, double* work, size_t work_elems, const int* any_active,
                             hipEvent_t* ev, int* flag_log) {
-    if (w < 1 || w > 32 || n < 64 || (n % 8) != 0 || (precision != 1 && precision != 2) ||
+    if (w < 1 || w > 32 || n < 64 || (n % 8) != 0 || precision < 1 || precision > 3 ||
         (reinterpret_cast<uintptr_t>(A16) & 15))
         return hipErrorInvalidValue;
     const int ntiles = (n + WR - 1) / WR;
@@ -258,14 +376,24 @@ hipError_t cg_dense_apply16(hipStream_t st, int precision, int n, int w, const u
     int kchunk = (n + ksplit - 1) / ksplit;
     kchunk = ((kchunk + KS * 2 * PF - 1) / (KS * 2 * PF)) * (KS * 2 * PF);
     ksplit = (n + kchunk - 1) / kchunk;
-    // workspace: Xh (n x 32 16-bit) then the FP32 partial tiles
-    const size_t xh_elems = ((size_t)n * 32 * sizeof(uint16_t) + 15) / 16 * 2;   // in doubles, 16-byte units
+    // workspace: Xh (n x 32 16-bit; three parts for BF16x3) then the FP32 partial tiles
+    const size_t parts = precision == 3 ? 3 : 1;
+    const size_t xh_elems = (parts * n * 32 * sizeof(uint16_t) + 15) / 16 * 2;   // in doubles, 16-byte units
     const size_t part_floats = (size_t)ksplit * ntiles * WAVE * 32;
     if (xh_elems + (part_floats + 1) / 2 > work_elems) return hipErrorInvalidValue;
     uint16_t* Xh = reinterpret_cast<uint16_t*>(work);
     float* part = reinterpret_cast<float*>(work + xh_elems);
     const dim3 pgrid((n + 255) / 256 < 64 ? (n + 255) / 256 : 64, 32);
-    if (precision == 1) {
+    if (precision == 3) {
+        hipLaunchKernelGGL(cg_dir_pack16_kernel<3>, pgrid, dim3(256), 0, st, n, w, P, R, beta, active, rr, first, Xh,
+                           any_active, flag_log);
+        if (ev) (void)hipEventRecord(ev[0], st);
+        hipLaunchKernelGGL(apply16x3_stream_kernel, dim3(ntiles, ksplit), dim3(64), 0, st, n, A16, Xh, kchunk, part,
+                           any_active);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL(apply16_reduce_kernel<3>, dim3(ntiles, 4), dim3(256), 0, st, n, w, ksplit, part, rr, Q, P,
+                           pq, any_active);
+    } else if (precision == 1) {
         hipLaunchKernelGGL(cg_dir_pack16_kernel<1>, pgrid, dim3(256), 0, st, n, w, P, R, beta, active, rr, first, Xh,
                            any_active, flag_log);
         if (ev) (void)hipEventRecord(ev[0], st);

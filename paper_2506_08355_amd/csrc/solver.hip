@@ -154,8 +154,9 @@ struct Solver {
         }
         prof_cols.push_back(cols);
         const double nn = (double)n, c = cols;
-        if (op->kind == 0 && prec != 0) {   // 16-bit operator and block, FP64 result
-            prof_b.push_back(2.0 * nn * nn + 2.0 * nn * c + 8.0 * nn * c);
+        if (op->kind == 0 && prec != 0) {   // 16-bit operator and block (3 parts each for BF16x3), FP64 result
+            const double parts = prec == 3 ? 3.0 : 1.0;
+            prof_b.push_back(parts * (2.0 * nn * nn + 2.0 * nn * c) + 8.0 * nn * c);
             prof_f.push_back(2.0 * nn * nn * c);
         } else if (op->kind == 0) {
             prof_b.push_back(8.0 * nn * nn + 16.0 * nn * c);
@@ -1004,7 +1005,7 @@ int solve_options(const lrep_solve_opts_t* opts, int64_t block, lrep_solve_opts_
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 2 || o.fused_cg < -1 || o.fused_cg > 1)
+    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 3 || o.fused_cg < -1 || o.fused_cg > 1)
         return LREP_EINVAL;
     return LREP_OK;
 }
@@ -1040,7 +1041,8 @@ int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_s
     size_t total = s.footprint();
     if (o.precision != 0 && op->kind == 0) {
         std::lock_guard<std::mutex> g(op->mu16);
-        if (op->prec16 != o.precision) total += 2 * (size_t)op->n * op->n * sizeof(uint16_t);
+        if (op->prec16 != o.precision)
+            total += 2 * (size_t)(o.precision == 3 ? 3 : 1) * op->n * op->n * sizeof(uint16_t);
     }
     *bytes = total;
     return LREP_OK;
@@ -1060,7 +1062,7 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
             op->K16buf.release();
             op->M16buf.release();
             op->prec16 = 0;
-            const size_t bytes = (size_t)op->n * op->n * sizeof(uint16_t);
+            const size_t bytes = (size_t)(o.precision == 3 ? 3 : 1) * op->n * op->n * sizeof(uint16_t);
             int rc = op->K16buf.alloc(op->ctx, bytes);
             if (rc == LREP_OK) rc = op->M16buf.alloc(op->ctx, bytes);
             if (rc != LREP_OK) return rc;

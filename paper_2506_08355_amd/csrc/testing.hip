@@ -127,14 +127,14 @@ int lrep_test_cg(lrep_op_t op, int which, int nw, const double* B, double* X, do
 }
 
 int lrep_test_convert16(lrep_ctx_t ctx, int precision, int n, const double* A, int64_t lda, uint16_t* out) {
-    if (!ctx || (precision != 1 && precision != 2) || n < 1 || lda < n || !A || !out) return LREP_EINVAL;
+    if (!ctx || precision < 1 || precision > 3 || n < 1 || lda < n || !A || !out) return LREP_EINVAL;
     (void)hipSetDevice(ctx->device);
     return finish(ctx, convert_operator16(ctx->stream, precision, n, A, lda, out));
 }
 
 int lrep_test_apply16(lrep_ctx_t ctx, int precision, int n, int cols, const uint16_t* A16, const double* X,
                       const double* rr, double* Y) {
-    if (!ctx || cols < 1 || cols > 32 || (precision != 1 && precision != 2) || n < 64 || (n % 8) != 0 || !A16 ||
+    if (!ctx || cols < 1 || cols > 32 || precision < 1 || precision > 3 || n < 64 || (n % 8) != 0 || !A16 ||
         !X || !rr || !Y)
         return LREP_EINVAL;
     (void)hipSetDevice(ctx->device);

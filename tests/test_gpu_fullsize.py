@@ -49,10 +49,12 @@ def solve(ctx, op, n, nev, block, window, tol, init, precision=0):
     return rc, st, lam, X, Y
 
 
-@pytest.mark.parametrize("zeros,seed,precision", [(0, 1002, 0), (8, 1012, 0), (0, 1002, 1), (0, 1002, 2)],
-                         ids=["dense8192", "dense8192_zero_variant", "dense8192_bf16_cg", "dense8192_fp16_cg"])
+@pytest.mark.parametrize("zeros,seed,precision", [(0, 1002, 0), (8, 1012, 0), (0, 1002, 1), (0, 1002, 2),
+                                                  (0, 1002, 3)],
+                         ids=["dense8192", "dense8192_zero_variant", "dense8192_bf16_cg", "dense8192_fp16_cg",
+                              "dense8192_bf16x3_cg"])
 def test_config2_full_size(ctx, zeros, seed, precision):
-    """The mixed-precision cases (CG applies in BF16 / FP16) are held to the
+    """The mixed-precision cases (CG applies in BF16 / FP16 / BF16x3) are held to the
     same bars: per pair, eigenvalue error against the exact spectrum <= 1e-10
     relative and FP64 residual <= 1e-8."""
     n, nev, block, window, tol = 8192, 64, 64, 32, 1e-10
@@ -190,11 +192,11 @@ def dense32768(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp64", "bf16_cg", "fp16_cg"])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3], ids=["fp64", "bf16_cg", "fp16_cg", "bf16x3_cg"])
 def test_config4_dense32768_full_size(ctx, dense32768, precision):
     """The mixed-precision configuration at its own size: n = 32768, nev 64,
-    block 64, window 32, tol 1e-10, the CG applies of Step 6 in FP64, BF16
-    or FP16 (FP32 accumulation), everything else FP64.  Every eigenvalue
+    block 64, window 32, tol 1e-10, the CG applies of Step 6 in FP64, BF16,
+    FP16 or BF16x3 (FP32 accumulation), everything else FP64.  Every eigenvalue
     within 1e-10 relative of the oracle's exact spectrum (the error of each
     pair is printed), residual <= 1e-8 and max |X^T Y - I| <= 1e-12 (device
     FP64 products, independent of the library)."""

@@ -321,6 +321,67 @@ def test_apply16_against_rounded_operands(ctx, precision, n, cols):
         assert np.abs(host(Yd) - exact).max() <= 2e-2 * np.abs(exact).max()
 
 
+def _split3_host(v):
+    """The three BF16 parts of FP64 values, each the rounding (to nearest
+    even) of what the earlier parts leave, as FP64 arrays."""
+    parts = []
+    r = np.array(v, dtype=np.float64)
+    for _ in range(3):
+        h = _round16(r, 1).to(torch.float64).numpy()
+        parts.append(h)
+        r = r - h
+    return parts
+
+
+@pytest.mark.parametrize("n", [64, 1001, 4104])
+def test_convert16_bf16x3_parts(ctx, n):
+    """BF16x3 operator copy: three BF16 matrices whose parts are bitwise the
+    host's successive roundings of the symmetric part, and whose sum carries
+    at least FP32's 24 bits (|S - (hi + mid + lo)| <= 2^-24 |S|)."""
+    rng = np.random.default_rng(n + 7)
+    lda = n + 3
+    A = rng.standard_normal((lda, n)) * (10.0 ** rng.uniform(-3, 3, (lda, n)))
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").T[:n]
+    out = torch.empty(3 * n * n, dtype=torch.int16, device="cuda:0")
+    L.lrep_test_convert16(ctx, 3, Ad, out)
+    S = 0.5 * (A[:n] + A[:n].T)
+    want = _split3_host(S)
+    got = out.cpu().view(torch.bfloat16).to(torch.float64).numpy().reshape(3, n, n).transpose(0, 2, 1)
+    for q in range(3):
+        assert np.array_equal(got[q], want[q]), (q, int((got[q] != want[q]).sum()))
+    assert np.all(np.abs(S - (got[0] + got[1] + got[2])) <= 2.0 ** -24 * np.abs(S))
+
+
+@pytest.mark.parametrize("n,cols", [(64, 5), (1000, 32), (4104, 19), (8192, 32)])
+def test_apply16_bf16x3_is_fp32_accurate(ctx, n, cols):
+    """The BF16x3 CG apply: the six part products of order <= 2 summed in
+    FP32 give the FP64 product to FP32 accuracy, |err_i| <= (n + 8) 2^-23
+    (|A| |X|)_i (16-bit products: 2e-2 of the largest entry), so a missing or
+    doubled part, a wrong part offset or the 16-bit layout shows at once.
+    Ragged k (1000), split k with a ragged last chunk (4104), the workload's
+    size (8192); columns of norm 1e-6 and 1e6."""
+    Kd, Md, _, _ = gen.dense_operator_device(n, 40 + n, "cuda:0")
+    rng = np.random.default_rng(n)
+    Xh = rng.standard_normal((n, cols))
+    Xh[:, 0] *= 1e-6
+    Xh[:, cols - 1] *= 1e6
+    rr = (Xh * Xh).sum(axis=0)
+    Xd = dev_colmajor(Xh, torch).T.contiguous().T
+    rrd = torch.from_numpy(rr).to("cuda:0")
+    Yd = dev_empty(n, cols, torch).T.contiguous().T
+    A16 = torch.empty(3 * n * n, dtype=torch.int16, device="cuda:0")
+    for Ad in (Kd, Md):
+        L.lrep_test_convert16(ctx, 3, Ad.T, A16)
+        L.lrep_test_apply16(ctx, 3, A16, Xd, rrd, Yd)
+        A = Ad.cpu().numpy()
+        exact = A @ Xh
+        bound = (n + 8) * 2.0 ** -23 * (np.abs(A) @ np.abs(Xh))
+        err = np.abs(host(Yd) - exact)
+        assert np.all(err <= bound), float((err / bound).max())
+        # far tighter than the BF16 product (~4e-3 relative)
+        assert (err / (np.abs(A) @ np.abs(Xh))).max() <= 1e-4
+
+
 @pytest.mark.parametrize("n,r", [(1502, 16), (20002, 100), (262144, 256)])
 @pytest.mark.parametrize("which", [0, 1])
 def test_fused_cg_matches_plain_cg_and_the_oracle(ctx, n, r, which):
