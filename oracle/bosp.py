@@ -60,9 +60,10 @@ Ritz pairs -- the window a -- feed Steps 5-6.  The X block keeps b columns
   * each returned pair is sign-normalised: the entry of x of largest
     magnitude is made positive (y flips with it).
   * Step 1 draws one standard-normal block and uses it for both U and V
-    (the paper asks only that U^T V be invertible; V = U makes U^T V = U^T U
-    SPD, whereas independent U and V give a badly conditioned biorthogonal
-    basis from which the iteration does not recover).
+    (the algorithm draws the columns at random and needs U^T V invertible;
+    V = U makes U^T V = U^T U SPD, so no restore of U^T V = I is needed at
+    the start; independent U and V, passed through ``init``, reach the same
+    pairs after a few restores by the biorthogonality monitor).
   * the projectors of Steps 5 and 6 are applied twice.  Both act on vectors
     that largely cancel near convergence (X^_a ~ E_a; W mostly along X~), so
     one application leaves them biorthogonal only to eps / (relative size

@@ -128,6 +128,27 @@ def test_config1_dense_n256():
     assert np.all(res.eps <= 1e-10)
 
 
+@pytest.mark.parametrize("n,seed,nev,block,window", [(256, 1001, 8, 16, 8), (600, 1005, 16, 16, 8)])
+def test_independent_start_blocks_reach_the_same_pairs(n, seed, nev, block, window):
+    """Step 1 of the algorithm draws U and V at random; the oracle (and the
+    library) take V = U (reading Z6).  Independent U and V must lead to the
+    same pairs: the biorthogonality monitor restores U^T V = I where the
+    independent start erodes it, and the iteration count stays within a few
+    iterations of the V = U start (measured: 22 vs 21 and 60 vs 66)."""
+    K, M, f = gen.dense_operator(n, seed)
+    op = oracle.DenseOperator(K, M)
+    U, V = gen.init_block(n, block + 2 * window, 7)
+    ref = exact.dense_spectrum(f.q1, f.k, f.q2, f.m, nev)
+    same = oracle.bosp_solve(op, nev, block, 1e-10, window=window, init=(U, U.copy()), maxit=400)
+    indep = oracle.bosp_solve(op, nev, block, 1e-10, window=window, init=(U, V), maxit=400)
+    for res in (same, indep):
+        assert res.converged and res.lam.size == nev
+        np.testing.assert_allclose(res.lam, ref, rtol=1e-10)
+        _invariants(op, res, f.norm_H())
+    assert indep.stats["rebiorth"] >= 1 and same.stats["rebiorth"] == 0
+    assert abs(indep.iterations - same.iterations) <= 0.15 * same.iterations + 2
+
+
 def test_commuting_case_closed_form():
     """Q1 = Q2: lambda_i = sqrt(k_i m_i) exactly."""
     n = 120
