@@ -157,7 +157,10 @@ def serve(args, np, torch, gen, L):
     in [512, 16384], low-rank n in [16384, 262144]); the default caps them
     (dense n <= 8192, low-rank n <= 32768) so that a run stays within a few
     minutes.  `--budget-gib` caps the context's HBM (requests then queue for
-    memory)."""
+    memory).  With `--sequential 1` the same requests also run one after
+    the other through the blocking lrep_solve on the same context (the
+    sequential rate the served rate is compared with); every served and
+    sequential result is checked (verify)."""
     rng = np.random.default_rng(1005)
     dev = torch.device("cuda:0")
     full = args.serve_sizes == "full"
@@ -189,52 +192,57 @@ def serve(args, np, torch, gen, L):
         window = block // 2 if block >= 32 else block
         reqs.append((k, nev, block, window))
 
-    def verify(results):
-        """Each served result against bars independent of the library: the
-        residual ||H z - lambda z|| / (||H|| ||z||) <= 1e-8 and max |X^T Y - I|
-        <= 1e-12 (torch FP64 products), and the eigenvalues against the
-        oracle's exact spectrum of the operator (dense: the factored closed
-        form; low rank: each eigenvalue bracketed at 1e-10 relative by the
-        inertia count, once per operator for the longest served prefix)."""
+    def check_vectors(j, lam, X, Y):
+        """One result against bars independent of the library: the residual
+        ||H z - lambda z|| / (||H|| ||z||) <= 1e-8 and max |X^T Y - I| <= 1e-12
+        (torch FP64 products).  Returns a failure record or None."""
+        k = reqs[j][0]
+        c = checks[k]
+        Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+        ld = torch.from_numpy(lam).to(dev)
+        if c["kind"] == "dense":
+            KX, MY = c["K"] @ Xd, c["M"] @ Yd
+        else:
+            KX = c["delta"][:, None] * Xd
+            MY = c["delta"][:, None] * Yd + 2.0 * (c["L"] @ (c["L"].T @ Yd))
+        res = torch.sqrt(((KX - Yd * ld) ** 2).sum(0) + ((MY - Xd * ld) ** 2).sum(0)) / (
+            c["normH"] * torch.sqrt((Xd ** 2).sum(0) + (Yd ** 2).sum(0)))
+        bi = float((Xd.T @ Yd - torch.eye(lam.size, dtype=torch.float64, device=dev)).abs().max())
+        if float(res.max()) > 1e-8 or bi > 1e-12:
+            return [j, "residual/biorth", float(res.max()), bi]
+        return None
+
+    def reference_values(lams):
+        """The reference eigenvalues of every operator some result in lams
+        (list of (request, lambda)) belongs to: dense, the oracle's factored
+        closed form for the longest prefix asked; low rank, the longest
+        returned prefix with each value bracketed at 1e-10 relative by the
+        oracle's inertia count.  Returns (ref, failures)."""
         from oracle import exact
-        bad = []
-        longest = {}
-        for j, (lam, X, Y) in results.items():
-            k = reqs[j][0]
+        bad, ref = [], {}
+        for k in sorted({reqs[j][0] for j, _ in lams}):
             c = checks[k]
-            Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
-            ld = torch.from_numpy(lam).to(dev)
-            if c["kind"] == "dense":
-                KX, MY = c["K"] @ Xd, c["M"] @ Yd
-            else:
-                KX = c["delta"][:, None] * Xd
-                MY = c["delta"][:, None] * Yd + 2.0 * (c["L"] @ (c["L"].T @ Yd))
-            res = torch.sqrt(((KX - Yd * ld) ** 2).sum(0) + ((MY - Xd * ld) ** 2).sum(0)) / (
-                c["normH"] * torch.sqrt((Xd ** 2).sum(0) + (Yd ** 2).sum(0)))
-            bi = float((Xd.T @ Yd - torch.eye(lam.size, dtype=torch.float64, device=dev)).abs().max())
-            if float(res.max()) > 1e-8 or bi > 1e-12:
-                bad.append([j, "residual/biorth", float(res.max()), bi])
-            if k not in longest or lam.size > longest[k].size:
-                longest[k] = lam
-        ref = {}
-        for k, lam in longest.items():
-            c = checks[k]
+            longest = max((lam for j, lam in lams if reqs[j][0] == k), key=lambda a: a.size)
             if c["kind"] == "dense":
                 ref[k] = exact.dense_spectrum_smallest(c["q1"].cpu().numpy(), c["k"], c["q2"].cpu().numpy(), c["m"],
-                                                       lam.size)
+                                                       longest.size)
             else:
-                lo = exact.casida_count_below_many(c["f"].delta, c["f"].L, lam * (1 - 1e-10))
-                hi = exact.casida_count_below_many(c["f"].delta, c["f"].L, lam * (1 + 1e-10))
-                if not all(lo[i] <= i and hi[i] >= i + 1 for i in range(lam.size)):
+                lo = exact.casida_count_below_many(c["f"].delta, c["f"].L, longest * (1 - 1e-10))
+                hi = exact.casida_count_below_many(c["f"].delta, c["f"].L, longest * (1 + 1e-10))
+                if not all(lo[i] <= i and hi[i] >= i + 1 for i in range(longest.size)):
                     bad.append([int(k), "bracket"])
-                ref[k] = lam
-        for j, (lam, X, Y) in results.items():
+                ref[k] = longest
+        return ref, bad
+
+    def check_values(lams, ref):
+        bad = []
+        for j, lam in lams:
             r = ref[reqs[j][0]][:lam.size]
             if np.abs(lam - r).max() > 1e-10 * r.max():
                 bad.append([j, "eigenvalues", float(np.abs(lam - r).max())])
         return bad
 
-    def run(arrivals):
+    def run(arrivals, keep):
         jobs, done = [], {}
         start = time.perf_counter()
         i = 0
@@ -254,22 +262,53 @@ def serve(args, np, torch, gen, L):
                 if rc == L.LREP_EAGAIN:
                     continue
                 j, ts, outs = pending.pop(t)
-                done[j] = (rc, (time.perf_counter() - ts) * 1e3, outs[:3])
+                done[j] = (rc, (time.perf_counter() - ts) * 1e3, outs[:3] if keep else None)
                 print(f"[serve] request {j} rc={rc} {done[j][1]:.0f} ms ({len(done)}/{len(reqs)})",
                       file=sys.stderr, flush=True)
             time.sleep(0.0005)
         return time.perf_counter() - start, done
 
-    closed_time, closed = run([0.0] * len(reqs))
+    seq_time, seq_bad, seq_lams = None, [], []
+    if args.sequential:
+        # the same requests one at a time through the blocking call
+        # (each result is checked right after its solve, outside the timed sum)
+        seq_time = 0.0
+        for j, (k, nev, block, window) in enumerate(reqs):
+            op, n = pool[k]
+            lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+            t1 = time.perf_counter()
+            rc, _ = L.lrep_solve(op, n, nev, block, 1e-8, L.make_opts(window=window, seed=17 + j, graphs=args.graphs),
+                                 lam, X, Y, ctx=ctx, check=False)
+            seq_time += time.perf_counter() - t1
+            if rc == L.LREP_OK:
+                f = check_vectors(j, lam, X, Y)
+                if f:
+                    seq_bad.append(f)
+                seq_lams.append((j, lam))
+            else:
+                seq_bad.append([j, "rc", rc])
+            if j % 16 == 15:
+                print(f"[serve] sequential {j + 1}/{len(reqs)}: {seq_time:.1f}s of solves, {len(seq_bad)} failures",
+                      file=sys.stderr, flush=True)
+    closed_time, closed = run([0.0] * len(reqs), False)
     rate = len(reqs) / closed_time
     gaps = rng.exponential(1.0 / (args.rho * rate), len(reqs))
     arrivals = np.cumsum(gaps) - gaps[0]
-    open_time, done = run(list(arrivals))
+    open_time, done = run(list(arrivals), True)
     lat = np.array([done[j][1] for j in range(len(reqs))])
     ok = all(done[j][0] == L.LREP_OK for j in range(len(reqs))) and all(
         closed[j][0] == L.LREP_OK for j in range(len(reqs)))
     tv = time.time()
-    bad = verify({j: done[j][2] for j in range(len(reqs)) if done[j][0] == L.LREP_OK})
+    bad = []
+    for j in range(len(reqs)):
+        if done[j][0] == L.LREP_OK:
+            f = check_vectors(j, *done[j][2])
+            if f:
+                bad.append(f)
+    served_lams = [(j, done[j][2][0]) for j in range(len(reqs)) if done[j][0] == L.LREP_OK]
+    ref, rbad = reference_values(served_lams + seq_lams)
+    bad += rbad + check_values(served_lams, ref)
+    seq_bad += check_values(seq_lams, ref)
     print(f"[serve] results checked in {time.time() - tv:.1f}s: {len(bad)} failures", file=sys.stderr, flush=True)
     failed = [[j, done[j][0], pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
               for j in range(len(reqs)) if done[j][0] != L.LREP_OK][:10]
@@ -291,6 +330,8 @@ def serve(args, np, torch, gen, L):
                    "hbm_budget_gib": args.budget_gib if args.budget_gib else None,
                    "operator_n": [n for _, n in pool]},
         "closed_loop_solves_per_s": round(rate, 3),
+        "sequential_solves_per_s": round(len(reqs) / seq_time, 3) if seq_time else None,
+        "sequential_failures": seq_bad[:10],
         "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "all_ok": ok and not bad, "oracle_failures": bad[:10], "failed": failed, "slowest": slow,
     }
@@ -321,7 +362,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="casida262144", choices=sorted(WORKLOADS) + ["serve"])
-    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=512, help="serve: number of requests (the configuration's 512)")
+    ap.add_argument("--sequential", type=int, default=1, choices=[0, 1],
+                    help="serve: also run the same requests one at a time through lrep_solve (the comparison)")
     ap.add_argument("--serve-sizes", choices=["reduced", "full"], default="reduced",
                     help="serve: operator size ranges (full: dense n <= 16384, low-rank n <= 262144)")
     ap.add_argument("--budget-gib", type=float, default=0.0, help="serve: HBM budget of the context (0: none)")
