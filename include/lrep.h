@@ -127,15 +127,26 @@ typedef struct lrep_solve_opts {
                               plain CG (L^T p and L (L^T p) as two passes, then
                               separate vector updates).  Same iteration, different
                               rounding order.                                         */
-    int32_t reserved0;     /* zero                                                    */
+    int32_t serve_batch;   /* served requests (lrep_submit) on dense or low-rank
+                              operators: 0 (default) -- a Step-6 CG solve that
+                              starts while another request's CG on the same
+                              operator (same CG settings) runs or waits joins it:
+                              the waiting solves run as one block CG over their
+                              concatenated columns (at most 32), the operator
+                              streamed once per step for all; every column's
+                              arithmetic is the one it has alone, so results are
+                              bitwise those of the request alone.  -1: never.
+                              Ignored by lrep_solve.                                 */
 } lrep_solve_opts_t;
 
 /* Per-solve statistics (all optional to read). */
 typedef struct lrep_stats {
     int64_t iterations;        /* outer iterations run                                 */
     int64_t n_converged;       /* eigenpairs written (== nev on LREP_OK)               */
-    int64_t applies_K;         /* column mat-vecs with K                               */
-    int64_t applies_M;         /* column mat-vecs with M                               */
+    int64_t applies_K;         /* column mat-vecs with K (served with batching: those
+                                  of the block CGs this request led, other requests'
+                                  columns included)                                  */
+    int64_t applies_M;         /* column mat-vecs with M (likewise)                    */
     int64_t mgs_drops;         /* columns dropped by MGS-Biorth breakdown handling      */
     int64_t locks;             /* moving-mechanism lock events                          */
     int64_t rebiorth;          /* biorthogonality restorations                          */
@@ -152,6 +163,10 @@ typedef struct lrep_stats {
     double  prof_bytes;        /* algorithmic bytes they move (operator read once,
                                   block read once, result written once)               */
     double  prof_flops;        /* algorithmic flops (2 n^2 w dense)                     */
+    int64_t cg_batched;        /* served: Step-6 CG solves of this request that ran
+                                  in one block CG with other requests' columns       */
+    int64_t cg_batch_columns;  /* served: CG columns of other requests that ran in
+                                  the block CGs this request's worker thread led    */
 } lrep_stats_t;
 
 /* Request for the serving interface (lrep_submit). */

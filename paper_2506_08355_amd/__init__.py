@@ -69,7 +69,7 @@ class lrep_solve_opts_t(ctypes.Structure):
         ("refresh", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
         ("fused_cg", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("serve_batch", ctypes.c_int32),
     ]
 
 
@@ -89,6 +89,8 @@ class lrep_stats_t(ctypes.Structure):
         ("prof_ms", ctypes.c_double),
         ("prof_bytes", ctypes.c_double),
         ("prof_flops", ctypes.c_double),
+        ("cg_batched", ctypes.c_int64),
+        ("cg_batch_columns", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -342,10 +344,11 @@ def lrep_destroy_op(op):
 
 
 def make_opts(window=0, maxit=0, ngs=0, cg_maxit=0, cg_tol=0.0, seed=0, init=None, result_on_device=False,
-              rebiorth_tol=0.0, profile=False, refresh=0, precision=0, graphs=0, fused_cg=0):
+              rebiorth_tol=0.0, profile=False, refresh=0, precision=0, graphs=0, fused_cg=0, serve_batch=0):
     o = lrep_solve_opts_t()
     o.graphs = graphs
     o.fused_cg = fused_cg
+    o.serve_batch = serve_batch
     o.window, o.maxit, o.ngs, o.cg_maxit, o.cg_tol, o.seed = window, maxit, ngs, cg_maxit, cg_tol, seed
     if init is not None:
         p, ld, dev = colmajor(init)

@@ -14,6 +14,7 @@ struct lrep_op_s : public Op {};
 namespace lrep {
 
 thread_local Reservation* t_reservation = nullptr;
+thread_local bool t_serving = false;
 
 DevBuf::~DevBuf() { release(); }
 
@@ -140,9 +141,11 @@ void worker_main(Ctx* c) {
         lk.unlock();
         Reservation rv{c, fp};
         t_reservation = c->budget ? &rv : nullptr;
+        t_serving = true;
         lrep_stats_t stats{};
         const int rc = solve(t.op, st, t.req.nev, t.req.block, t.req.tol, &t.req.opts, t.req.lambda, t.req.X,
                              t.req.Y, t.req.ldxy, &stats);
+        t_serving = false;
         t_reservation = nullptr;
         lk.lock();
         if (c->budget) {
@@ -555,7 +558,7 @@ int lrep_submit(lrep_ctx_t c, lrep_op_t op, const lrep_request_t* req, lrep_tick
         req->ldxy < op->n)
         return LREP_EINVAL;
     size_t fp = 0;
-    const int frc = solve_footprint(op, req->nev, req->block, req->tol, &req->opts, &fp);
+    const int frc = solve_footprint(op, req->nev, req->block, req->tol, &req->opts, &fp, true);
     if (frc != LREP_OK) return frc;
     std::lock_guard<std::mutex> g(c->q_mu);
     if (c->stopping) return LREP_EINVAL;

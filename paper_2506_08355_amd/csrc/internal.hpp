@@ -19,6 +19,7 @@
 namespace lrep {
 
 struct Ctx;
+struct CgJob;   // a served Step-6 CG solve waiting to be batched (solver.hip)
 
 // A served request's admission reserves its whole footprint against the
 // context's budget before the solve starts; the solve's own allocations (on
@@ -28,6 +29,8 @@ struct Reservation {
     size_t left;
 };
 extern thread_local Reservation* t_reservation;
+// true on a serving worker thread while it runs a request's solve
+extern thread_local bool t_serving;
 
 // Device allocation charged against the context's HBM budget.
 struct DevBuf {
@@ -92,6 +95,12 @@ struct Op {
     const uint16_t* K16() const { return reinterpret_cast<const uint16_t*>(K16buf.p); }
     const uint16_t* M16() const { return reinterpret_cast<const uint16_t*>(M16buf.p); }
     bool null_on_M() const { return (flags & LREP_NULL_ON_M) != 0; }
+    // serving: Step-6 CG solves of concurrent requests waiting to run as one
+    // block CG (solver.hip, Solver::cg_batched)
+    std::mutex batch_mu;
+    std::condition_variable batch_cv;
+    std::vector<CgJob*> batch_queue;
+    bool batch_running = false;
 };
 
 struct Ctx {
@@ -137,7 +146,8 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
 // Device bytes a solve with these arguments charges to the context (its
 // workspaces, and 16-bit operator copies it would make); LREP_EINVAL for
 // arguments the solve would reject.  No device work.
-int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes);
+int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes,
+                    bool served = false);
 
 // Null-space preparation (solver.hip): X0t (device, n x r, ld n) -> op->X0, op->Y0.
 int prepare_nullspace(Op* op, hipStream_t st, int64_t r, const double* X0t_dev);

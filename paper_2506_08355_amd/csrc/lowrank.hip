@@ -818,10 +818,12 @@ hipError_t lowrank_apply_M_rows(hipStream_t st, int n, int r, int w, const doubl
 
 
 namespace {
+// row chunks of the diagonal step and of the initialisation: a function of n
+// alone, so that a column's sums are taken in the same order whatever the
+// number of columns solved with it
 int fcg_chunks(int n, int w) {
-    int nch = (1024 + w - 1) / w;
-    nch = std::min(nch, std::max(1, n / 1024));
-    return std::max(1, std::min(nch, 256));
+    (void)w;
+    return std::max(1, std::min(32, n / 1024));
 }
 int fcg_groups(int n) {
     const int ntile = (n + PT - 1) / PT;

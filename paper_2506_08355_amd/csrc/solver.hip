@@ -52,6 +52,25 @@
 
 namespace lrep {
 
+// A Step-6 CG solve waiting to run in a block CG shared with other served
+// requests on the same operator (Solver::cg_batched).
+struct CgJob {
+    const void* owner;      // the Solver whose job it is
+    int which, nw, maxit, precision, fused;
+    double tol;
+    const double* B;        // right-hand sides (device, ld ldb)
+    int64_t ldb;
+    double* X;              // the owner's CG solution block (device, n x nw, ld n)
+    hipEvent_t ready;       // recorded on the owner's stream once B is written
+    hipEvent_t done;        // recorded on the running stream once X is written
+    int rc = LREP_OK;
+    bool finished = false;
+    bool shared = false;    // ran together with other requests' columns
+    bool compatible(const CgJob& o) const {
+        return which == o.which && maxit == o.maxit && tol == o.tol && precision == o.precision && fused == o.fused;
+    }
+};
+
 namespace {
 
 constexpr double MGS_COS_TOL = 1e-10;
@@ -85,6 +104,11 @@ struct Solver {
     Op* op;
     hipStream_t st;
     int64_t n;
+    // served Step-6 CG solves may run batched with other requests' (set by
+    // solve_configure; the CG buffers then hold 32 columns)
+    bool batch = false;
+    DevBuf bcomb;                                  // gathered right-hand sides of a batch (n x 32, ld n)
+    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
     int64_t ldn = 0;   // leading dimension of the blocks (solver_ld(n), set by buffers())
     int b, w, cap, nev, r0;
     double tol;
@@ -129,6 +153,8 @@ struct Solver {
     ~Solver() {
         for (auto& g : graphs6) (void)hipGraphExecDestroy(g.exec);
         if (np_ev) (void)hipEventDestroy(np_ev);
+        if (ev_ready) (void)hipEventDestroy(ev_ready);
+        if (ev_done) (void)hipEventDestroy(ev_done);
         if (hs) (void)hipHostFree(hs);
         if (note_h) (void)hipHostFree(note_h);
         for (auto e : prof_ev) (void)hipEventDestroy(e);
@@ -277,10 +303,14 @@ struct Solver {
         CR(f(Xc, col * nev));
         CR(f(Yc, col * nev));
         const size_t cw = (size_t)std::max(w, 1);
-        CR(f(cgX, col * cw));
-        CR(f(cgR, col * cw));
-        CR(f(cgP, col * cw));
-        CR(f(cgQ, col * cw));
+        // the CG state (ld n): 32 columns when the solve may lead a batch
+        const size_t cwg = batch ? std::max<size_t>(cw, 32) : cw;
+        const size_t coln = (size_t)n * sizeof(double);
+        CR(f(cgX, std::max(col * cw, coln * cwg)));
+        CR(f(cgR, std::max(col * cw, coln * cwg)));
+        CR(f(cgP, std::max(col * cw, coln * cwg)));
+        CR(f(cgQ, std::max(col * cw, coln * cwg)));
+        if (batch) CR(f(bcomb, coln * 32));
         CR(f(Zs, col * cw));
         CR(f(Ws, col * cw));
         CR(f(rhs, col * cw));
@@ -326,6 +356,10 @@ struct Solver {
         CK(hipMemsetAsync(ismall.p, 0, ismall.bytes, st));
         CK(hipHostMalloc((void**)&hs, sizeof(HostStatus), hipHostMallocDefault));
         CK(hipEventCreateWithFlags(&np_ev, hipEventDisableTiming));
+        if (batch) {
+            CK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
+            CK(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
+        }
         CK(hipHostMalloc((void**)&note_h, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent));
         *note_h = 0;
         CK(hipHostGetDevicePointer((void**)&note_d, note_h, 0));
@@ -474,6 +508,110 @@ struct Solver {
         CK(hipMemcpyAsync(hs->status, status, sizeof(int) * ST_COUNT, hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         return LREP_OK;
+    }
+
+    // Step-6 CG of a served request, batched with other requests on the same
+    // operator (continuous batching of the CG applies).  The job waits in the
+    // operator's queue while another batch runs; the thread whose job is
+    // pending when no batch runs leads the next one: its own job first, then
+    // the queued jobs with the same CG settings, up to 32 columns.  The
+    // leader gathers the right-hand sides (after each owner's `ready` event),
+    // runs one CG on its own stream and CG state, and hands every other job
+    // its columns (then `done`).  A thread leads only batches holding its own
+    // job, so no leader writes the CG state of a thread that runs anything.
+    // Every CG kernel treats the columns independently (the same arithmetic in
+    // the same order whatever the block width and position), so each column's
+    // result is bitwise the one it has alone.
+    int cg_batched(int which, const double* B, int64_t ldb, int nw, double cgtol, int maxit) {
+        CgJob job{};
+        job.owner = this;
+        job.which = which;
+        job.nw = nw;
+        job.maxit = maxit;
+        job.precision = o.precision;
+        job.fused = o.fused_cg;
+        job.tol = cgtol;
+        job.B = B;
+        job.ldb = ldb;
+        job.X = cgX.p;
+        job.ready = ev_ready;
+        job.done = ev_done;
+        CK(hipEventRecord(ev_ready, st));
+        std::unique_lock<std::mutex> lk(op->batch_mu);
+        op->batch_queue.push_back(&job);
+        while (!job.finished) {
+            if (op->batch_running) {
+                op->batch_cv.wait(lk);
+                continue;
+            }
+            // lead a batch: this job first, then compatible waiting jobs
+            std::vector<CgJob*> grp{&job};
+            int total = nw;
+            auto& q = op->batch_queue;
+            for (auto it = q.begin(); it != q.end();) {
+                CgJob* j = *it;
+                if (j == &job) {
+                    it = q.erase(it);
+                } else if (j->compatible(job) && total + j->nw <= 32) {
+                    grp.push_back(j);
+                    total += j->nw;
+                    it = q.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            op->batch_running = true;
+            lk.unlock();
+            const int rc = run_batch(grp, total);
+            lk.lock();
+            for (CgJob* j : grp) {
+                j->rc = rc;
+                j->shared = grp.size() > 1;
+                j->finished = true;
+            }
+            op->batch_running = false;
+            op->batch_cv.notify_all();
+        }
+        lk.unlock();
+        if (job.shared) stats.cg_batched++;
+        if (job.rc != LREP_OK) return job.rc;
+        // led by another thread: continue after its hand-over
+        CK(hipStreamWaitEvent(st, ev_done, 0));
+        return LREP_OK;
+    }
+
+    // one block CG over the jobs' columns (grp[0] is this solver's own job)
+    int run_batch(const std::vector<CgJob*>& grp, int total) {
+        const CgJob& mine = *grp[0];
+        if (grp.size() == 1) {
+            CR(cg(mine.which, mine.B, mine.ldb, mine.nw, mine.tol, mine.maxit, false));
+            CK(hipEventRecord(mine.done, st));
+            return LREP_OK;
+        }
+        int off = 0;
+        for (const CgJob* j : grp) {
+            if (j->owner != this) CK(hipStreamWaitEvent(st, j->ready, 0));
+            CK(copy_cols(st, (int)n, j->nw, j->B, j->ldb, bcomb.p + (size_t)off * n, n));
+            off += j->nw;
+        }
+        CR(cg(mine.which, bcomb.p, n, total, mine.tol, mine.maxit, false));
+        off = 0;
+        for (const CgJob* j : grp) {
+            // this solver's own columns are already in place (offset 0 of cgX)
+            if (j->owner != this) {
+                CK(copy_cols(st, (int)n, j->nw, cgX.p + (size_t)off * n, n, j->X, n));
+                stats.cg_batch_columns += j->nw;
+            }
+            off += j->nw;
+        }
+        for (const CgJob* j : grp) CK(hipEventRecord(j->done, st));
+        return LREP_OK;
+    }
+
+    // Step 6's CG: batched with other served requests where allowed
+    int cg_step6(int which, const double* B, int64_t ldb, int nw, double cgtol, int maxit) {
+        if (batch && nw <= 32) return cg_batched(which, B, ldb, nw, cgtol, maxit);
+        return cg(which, B, ldb, nw, cgtol, maxit, false);
     }
 
     // Gram C = A^T B for segment lists
@@ -783,10 +921,10 @@ int Solver::run(double* lambda_out, double* X_out, double* Y_out, int64_t ldxy) 
         auto step6 = [&]() -> int {
             for (int j = 0; j < o.ngs; ++j) {
                 CK(gs_rhs(st, (int)n, nw, j == 0 ? nullptr : Ws.p, ldn, NX, NMY, ldn, wincol, lamw, rhs.p, ldn));
-                CR(cg(1, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit, false));
+                CR(cg_step6(1, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit));
                 CK(copy_cols(st, (int)n, nw, cgX.p, n, Zs.p, ldn));
                 CK(gs_rhs(st, (int)n, nw, Zs.p, ldn, NY, NKX, ldn, wincol, lamw, rhs.p, ldn));
-                CR(cg(0, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit, false));
+                CR(cg_step6(0, rhs.p, ldn, nw, o.cg_tol, o.cg_maxit));
                 CK(copy_cols(st, (int)n, nw, cgX.p, n, Ws.p, ldn));
             }
             return LREP_OK;
@@ -1005,17 +1143,22 @@ int solve_options(const lrep_solve_opts_t* opts, int64_t block, lrep_solve_opts_
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 3 || o.fused_cg < -1 || o.fused_cg > 1)
+    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 3 || o.fused_cg < -1 || o.fused_cg > 1 ||
+        o.serve_batch < -1 || o.serve_batch > 0)
         return LREP_EINVAL;
     return LREP_OK;
 }
 
 // the solver's shape from the arguments (no device work); LREP_EINVAL for sizes out of range
 int solve_configure(Solver& s, Op* op, hipStream_t st, int64_t nev, int64_t block, double tol,
-                    const lrep_solve_opts_t& o) {
+                    const lrep_solve_opts_t& o, bool served = false) {
     s.op = op;
     s.st = st;
     s.n = op->n;
+    // served solves on dense or low-rank operators may batch their Step-6 CG
+    // with other requests' (not under graph capture or per-launch profiling)
+    s.batch = served && o.serve_batch == 0 && (op->kind == 0 || op->kind == 1) && o.graphs != 1 && !o.profile &&
+              o.window <= 32;
     if (o.precision != 0 && op->kind == 0 && (op->n % 8 != 0 || op->n < 64)) return LREP_EINVAL;
     if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
     s.o = o;
@@ -1033,11 +1176,12 @@ int solve_configure(Solver& s, Op* op, hipStream_t st, int64_t nev, int64_t bloc
 }
 }  // namespace
 
-int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes) {
+int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_solve_opts_t* opts, size_t* bytes,
+                    bool served) {
     lrep_solve_opts_t o;
     CR(solve_options(opts, block, o));
     Solver s;
-    CR(solve_configure(s, op, nullptr, nev, block, tol, o));
+    CR(solve_configure(s, op, nullptr, nev, block, tol, o, served));
     size_t total = s.footprint();
     if (o.precision != 0 && op->kind == 0) {
         std::lock_guard<std::mutex> g(op->mu16);
@@ -1053,7 +1197,7 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
     lrep_solve_opts_t o;
     CR(solve_options(opts, block, o));
     Solver s;
-    CR(solve_configure(s, op, st, nev, block, tol, o));
+    CR(solve_configure(s, op, st, nev, block, tol, o, t_serving));
     if (ldxy < op->n || !lambda || !X || !Y) return LREP_EINVAL;
     if (o.precision != 0 && op->kind == 0) {
         // 16-bit copies of K and M for the mixed-precision CG applies

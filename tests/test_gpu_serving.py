@@ -224,3 +224,44 @@ def test_cancel_queued_request(served):
             assert rc == L.LREP_ECANCELED
         else:
             assert rc == L.LREP_OK
+
+
+def test_concurrent_cg_solves_run_batched_and_bitwise_alone(served):
+    """Continuous batching of Step 6: eight requests on one operator at once
+    (window 8, so up to four jobs fill a 32-column block CG) -- their CG
+    solves run as shared block CGs (stats: cg_batched, cg_batch_columns),
+    every result bitwise the request's result alone, and the same with
+    batching switched off (serve_batch = -1)."""
+    ctx, ops, sizes, _, _, _ = served
+    for o, nev, block, window in ((0, 8, 16, 8), (2, 8, 16, 8)):
+        n = sizes[o]
+        U = np.asfortranarray(gen.init_block(n, block + 2 * window, 300 + o)[0])
+        lam0, X0, Y0 = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+        rc, _ = L.lrep_solve(ops[o], n, nev, block, 1e-8, L.make_opts(window=window, init=U), lam0, X0, Y0, ctx=ctx)
+        assert rc == L.LREP_OK
+        for batch in (0, -1):
+            jobs = []
+            for c in range(8):
+                lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+                opts = L.make_opts(window=window, init=U, serve_batch=batch)
+                jobs.append((L.lrep_submit(ctx, ops[o], nev, block, 1e-8, opts, lam, X, Y), lam, X, Y, opts))
+            stats, deadline = {}, time.time() + 120
+            while len(stats) < len(jobs) and time.time() < deadline:
+                for t, *_ in jobs:
+                    if t not in stats:
+                        rc, st = L.lrep_poll(ctx, t)
+                        if rc != L.LREP_EAGAIN:
+                            assert rc == L.LREP_OK, (o, batch, rc)
+                            stats[t] = st
+                time.sleep(0.002)
+            assert len(stats) == len(jobs), "served requests did not finish"
+            for t, lam, X, Y, _ in jobs:
+                assert np.array_equal(lam, lam0), (o, batch)
+                assert np.array_equal(X, X0), (o, batch)
+                assert np.array_equal(Y, Y0), (o, batch)
+            batched = sum(st.cg_batched for st in stats.values())
+            shared_cols = sum(st.cg_batch_columns for st in stats.values())
+            if batch == 0:
+                assert batched > 0 and shared_cols > 0, (o, batched, shared_cols)
+            else:
+                assert batched == 0 and shared_cols == 0, (o, batched, shared_cols)
