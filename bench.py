@@ -168,14 +168,19 @@ def serve(args, np, torch, gen, L):
     ctx = L.lrep_init(0, int(args.budget_gib * (1 << 30)))
     pool, t0 = [], time.time()
     checks = []              # per operator: what the served results are checked against
-    for i in range(6):       # dense, n log-uniform [512, dmax], multiple of 64
+    shared = args.serve_pool == "shared"
+    for i in range(1 if shared else 6):       # dense, n log-uniform [512, dmax], multiple of 64
         n = int(64 * round(np.exp(rng.uniform(np.log(512), np.log(dmax))) / 64))
+        if shared:
+            n = 8192
         Kd, Md, kk, mm, Q1, Q2 = gen.dense_operator_device(n, 2000 + i, dev, return_factors=True)
         pool.append((L.lrep_create_dense(ctx, Kd.T, Md.T), n))
         checks.append(dict(kind="dense", K=Kd, M=Md, q1=Q1, q2=Q2, k=kk, m=mm, normH=float(max(kk.max(), mm.max()))))
-    for i in range(6):       # low rank, n log-uniform [16384, lmax], rank uniform {64..256}
+    for i in range(1 if shared else 6):       # low rank, n log-uniform [16384, lmax], rank uniform {64..256}
         n = int(64 * round(np.exp(rng.uniform(np.log(16384), np.log(lmax))) / 64))
         r = int(rng.integers(64, 257))
+        if shared:
+            n, r = 65536, 128
         f = gen.casida_factors(n, r, 3000 + i)
         dd = torch.from_numpy(f.delta).to(dev)
         Ld = torch.from_numpy(np.ascontiguousarray(f.L.T)).to(dev).T
@@ -185,11 +190,16 @@ def serve(args, np, torch, gen, L):
     torch.cuda.synchronize()
     print(f"[serve] operator pool ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     reqs = []
+    nd = 1 if shared else 6
     for i in range(args.requests):
-        k = int(rng.integers(0, 6)) + (6 if rng.uniform() < 0.5 else 0)
+        k = int(rng.integers(0, nd)) + (nd if rng.uniform() < 0.5 else 0)
         nev = int(rng.integers(4, 65))
         block = 16 * ((nev + 15) // 16)
         window = block // 2 if block >= 32 else block
+        if shared:
+            # small windows, so that up to four concurrent CG solves share one 32-column block
+            nev = int(rng.integers(4, 17))
+            block, window = 16, 8
         reqs.append((k, nev, block, window))
 
     def check_vectors(j, lam, X, Y):
@@ -253,7 +263,7 @@ def serve(args, np, torch, gen, L):
                 k, nev, block, window = reqs[i]
                 op, n = pool[k]
                 lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
-                opts = L.make_opts(window=window, seed=17 + i, graphs=args.graphs)
+                opts = L.make_opts(window=window, seed=17 + i, graphs=args.graphs, serve_batch=args.serve_batch)
                 t = L.lrep_submit(ctx, op, nev, block, 1e-8, opts, lam, X, Y)
                 pending[t] = (i, time.perf_counter(), (lam, X, Y, opts))
                 i += 1
@@ -262,7 +272,8 @@ def serve(args, np, torch, gen, L):
                 if rc == L.LREP_EAGAIN:
                     continue
                 j, ts, outs = pending.pop(t)
-                done[j] = (rc, (time.perf_counter() - ts) * 1e3, outs[:3] if keep else None)
+                done[j] = (rc, (time.perf_counter() - ts) * 1e3, outs[:3] if keep else None,
+                           (st.cg_batched, st.cg_batch_columns))
                 print(f"[serve] request {j} rc={rc} {done[j][1]:.0f} ms ({len(done)}/{len(reqs)})",
                       file=sys.stderr, flush=True)
             time.sleep(0.0005)
@@ -310,10 +321,10 @@ def serve(args, np, torch, gen, L):
     bad += rbad + check_values(served_lams, ref)
     seq_bad += check_values(seq_lams, ref)
     print(f"[serve] results checked in {time.time() - tv:.1f}s: {len(bad)} failures", file=sys.stderr, flush=True)
-    failed = [[j, done[j][0], pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
+    failed = [[j, done[j][0], pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < nd else "lowrank"]
               for j in range(len(reqs)) if done[j][0] != L.LREP_OK][:10]
     slowest = sorted(range(len(reqs)), key=lambda j: -done[j][1])[:5]
-    slow = [[j, round(done[j][1], 1), pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < 6 else "lowrank"]
+    slow = [[j, round(done[j][1], 1), pool[reqs[j][0]][1], reqs[j][1], "dense" if reqs[j][0] < nd else "lowrank"]
             for j in slowest]
     for op, _ in pool:
         L.lrep_destroy_op(op)
@@ -323,13 +334,19 @@ def serve(args, np, torch, gen, L):
         "value": round(len(reqs) / open_time, 3), "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
         "warmup": 0, "ms_per_step": round(open_time * 1e3 / len(reqs), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"serving: 6 dense (n log-uniform 512-{dmax}) + 6 low-rank (n log-uniform "
-                               f"16384-{lmax}, rank 64-256) operators, requests 50/50, nev uniform 4-64, tol 1e-8, "
-                               f"Poisson arrivals at rho={args.rho} of the closed-loop rate",
+        "config": {"workload": (f"serving: 6 dense (n log-uniform 512-{dmax}) + 6 low-rank (n log-uniform "
+                                f"16384-{lmax}, rank 64-256) operators, requests 50/50, nev uniform 4-64, tol 1e-8, "
+                                f"Poisson arrivals at rho={args.rho} of the closed-loop rate") if not shared else
+                               (f"serving, shared operators: one dense (n=8192) and one low-rank (n=65536, rank 128) "
+                                f"operator, requests 50/50, nev uniform 4-16, block 16, window 8, tol 1e-8, Poisson "
+                                f"arrivals at rho={args.rho} of the closed-loop rate"),
+                   "cg_batching": args.serve_batch == 0,
                    "requests": len(reqs), "workers": 4,
                    "hbm_budget_gib": args.budget_gib if args.budget_gib else None,
                    "operator_n": [n for _, n in pool]},
         "closed_loop_solves_per_s": round(rate, 3),
+        "cg_solves_batched": int(sum(done[j][3][0] for j in range(len(reqs)))),
+        "cg_columns_shared": int(sum(done[j][3][1] for j in range(len(reqs)))),
         "sequential_solves_per_s": round(len(reqs) / seq_time, 3) if seq_time else None,
         "sequential_failures": seq_bad[:10],
         "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
@@ -363,6 +380,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="casida262144", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests (the configuration's 512)")
+    ap.add_argument("--serve-pool", choices=["mixed", "shared"], default="mixed",
+                    help="serve: the configuration's pool of 6 dense + 6 low-rank operators, or 'shared': every "
+                         "request on one dense (n = 8192) or one low-rank (n = 65536, rank 128) operator")
+    ap.add_argument("--serve-batch", type=int, default=0, choices=[-1, 0],
+                    help="serve: Step-6 CG solves of concurrent requests on one operator batched (0) or not (-1)")
     ap.add_argument("--sequential", type=int, default=1, choices=[0, 1],
                     help="serve: also run the same requests one at a time through lrep_solve (the comparison)")
     ap.add_argument("--serve-sizes", choices=["reduced", "full"], default="reduced",

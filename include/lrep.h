@@ -129,11 +129,12 @@ typedef struct lrep_solve_opts {
                               rounding order.                                         */
     int32_t serve_batch;   /* served requests (lrep_submit) on dense or low-rank
                               operators: 0 (default) -- a Step-6 CG solve that
-                              starts while another request's CG on the same
-                              operator (same CG settings) runs or waits joins it:
-                              the waiting solves run as one block CG over their
-                              concatenated columns (at most 32), the operator
-                              streamed once per step for all; every column's
+                              starts while a CG of another request on the same
+                              operator (same CG settings) runs on the device
+                              waits for it; the solves then waiting run as one
+                              block CG over their concatenated columns (at most
+                              32), the operator streamed once per step for all
+                              (one such block CG per operator at a time); every column's
                               arithmetic is the one it has alone, so results are
                               bitwise those of the request alone.  -1: never.
                               Ignored by lrep_solve.                                 */

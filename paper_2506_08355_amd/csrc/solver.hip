@@ -512,9 +512,10 @@ struct Solver {
 
     // Step-6 CG of a served request, batched with other requests on the same
     // operator (continuous batching of the CG applies).  The job waits in the
-    // operator's queue while another batch runs; the thread whose job is
-    // pending when no batch runs leads the next one: its own job first, then
-    // the queued jobs with the same CG settings, up to 32 columns.  The
+    // operator's queue while another batch runs (until the device has finished
+    // it); the thread whose job is pending when no batch runs leads the next
+    // one: its own job first, then the queued jobs with the same CG settings,
+    // up to 32 columns.  The
     // leader gathers the right-hand sides (after each owner's `ready` event),
     // runs one CG on its own stream and CG state, and hands every other job
     // its columns (then `done`).  A thread leads only batches holding its own
@@ -562,7 +563,13 @@ struct Solver {
             }
             op->batch_running = true;
             lk.unlock();
-            const int rc = run_batch(grp, total);
+            int rc = run_batch(grp, total);
+            // the batch holds the operator until the device has run it: solves
+            // that start meanwhile queue up and form the next batch
+            if (rc == LREP_OK) {
+                const hipError_t e = hipEventSynchronize(job.done);
+                if (e != hipSuccess) rc = dev_fail(e, "hipEventSynchronize(batch done)");
+            }
             lk.lock();
             for (CgJob* j : grp) {
                 j->rc = rc;
