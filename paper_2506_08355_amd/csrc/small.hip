@@ -79,14 +79,32 @@ __device__ __forceinline__ double wsum(double v) {
 // blocked right-looking on an LDS copy (blocks of CB = 16 columns), 256
 // threads per matrix:
 //   (a) the diagonal block is factored by one wavefront in registers, lane i
-//       holding row i, pivots and column entries broadcast with readlane;
+//       holding row i, the pivot broadcast with readlane and each scaled
+//       column through LDS (L(k,k) = a_kk / sqrt(a_kk) with a full-precision
+//       reciprocal square root);
 //   (b) the panel below it is solved row by row (L_pd = A_pd L_dd^{-T}), one
-//       thread per row;
+//       thread per row, multiplying by the reciprocals 1 / L(k,k);
 //   (c) the trailing matrix takes the rank-CB update A -= L_pd L_pd^T in
 //       4 x 4 register tiles.
 // A non-positive pivot sets status[ST_NOTSPD].
 // ---------------------------------------------------------------------------
 constexpr int CB = 16;
+
+// 1/x and 1/sqrt(x) to full FP64 precision: the hardware estimates are good
+// to ~2^-24, two Newton steps bring them to rounding level.
+__device__ __forceinline__ double rcp2(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq2(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x * r;
+    r = fma(r, fma(-h, r, 0.5), r);
+    h = 0.5 * x * r;
+    return fma(r, fma(-h, r, 0.5), r);
+}
+
 
 __device__ __forceinline__ double rdlane(double v, int l) {
     int2 p = __builtin_bit_cast(int2, v);
@@ -99,44 +117,69 @@ __global__ __launch_bounds__(256) void chol2_kernel(int d, const double* __restr
                                                    const double* __restrict__ Mh, int64_t ldh,
                                                    double* __restrict__ scratch, int* __restrict__ status) {
     __shared__ double S[kMaxD * LD];
+    __shared__ double colb[CB], dinv[CB];
     __shared__ int fail;
     const double* A = blockIdx.x == 0 ? Kh : Mh;
     double* L = scratch + (size_t)blockIdx.x * D2;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid % WAVE, wid = tid / WAVE;
-    for (int idx = tid; idx < d * d; idx += nt) {
-        const int i = idx % d, j = idx / d;
-        if (j <= i) S[i * LD + j] = 0.5 * (A[(int64_t)j * ldh + i] + A[(int64_t)i * ldh + j]);
+    // column c of A into row c of S (S[c LD + r] = A(r, c)): coalesced reads,
+    // eight columns in flight per wavefront
+    constexpr int NW = 256 / WAVE;
+    for (int c0 = wid; c0 < d; c0 += 8 * NW) {
+        double v0[8], v1[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k * NW;
+            const double* col = A + (int64_t)c * ldh;
+            v0[k] = (c < d && lane < d) ? col[lane] : 0.0;
+            v1[k] = (c < d && lane + WAVE < d) ? col[lane + WAVE] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k * NW;
+            if (c < d) {
+                S[c * LD + lane] = v0[k];
+                S[c * LD + lane + WAVE] = v1[k];
+            }
+        }
     }
     if (tid == 0) fail = 0;
     __syncthreads();
+    // the symmetric part into the lower triangle: for i > j, S[i LD + j]
+    // holds A(j, i) and S[j LD + i] holds A(i, j) (never written here); the
+    // diagonal is already A(i, i)
+    for (int i = 1 + wid; i < d; i += NW)
+        for (int j = lane; j < i; j += WAVE) S[i * LD + j] = 0.5 * (S[i * LD + j] + S[j * LD + i]);
+    __syncthreads();
     for (int kb = 0; kb < d; kb += CB) {
         const int nb = min(CB, d - kb);
-        // (a) diagonal block
+        // (a) diagonal block, one wavefront: lane i holds row i; at step k the
+        //     pivot comes from lane k (readlane), the scaled column k goes
+        //     through LDS to every lane (a wavefront sees its own LDS writes
+        //     in order), and 1 / L(k,k) is kept for the panel solve
         if (wid == 0) {
+            // rows past nb (a short last block) are padded with the identity,
+            // so every step runs unpredicated
             double r[CB];
 #pragma unroll
             for (int j = 0; j < CB; ++j)
-                r[j] = (lane < nb && j <= lane) ? S[(kb + lane) * LD + kb + j] : 0.0;
+                r[j] = lane < nb ? (j <= lane ? S[(kb + lane) * LD + kb + j] : 0.0) : (j == lane ? 1.0 : 0.0);
             bool bad = false;
 #pragma unroll
             for (int k = 0; k < CB; ++k) {
-                if (k < nb && !bad) {
-                    const double piv = rdlane(r[k], k);
-                    if (!(piv > 0.0)) {
-                        bad = true;
-                    } else {
-                        const double lkk = sqrt(piv);
-                        const double inv = 1.0 / lkk;
-                        r[k] = (lane == k) ? lkk : (lane > k ? r[k] * inv : r[k]);
+                const double piv = rdlane(r[k], k);
+                bad = bad || !(piv > 0.0);   // uniform; later steps may run on NaN, never stored
+                const double inv = rsq2(piv);
+                const double lk = (lane == k) ? piv * inv : r[k] * inv;
+                r[k] = (lane >= k) ? lk : r[k];
+                if (lane < CB) colb[lane] = lk;
+                if (lane == 0) dinv[k] = inv;
+                __builtin_amdgcn_wave_barrier();
+                // entries above the diagonal (j > lane) take values that are never
+                // read or stored
 #pragma unroll
-                        for (int j = k + 1; j < CB; ++j) {
-                            if (j < nb) {
-                                const double ljk = rdlane(r[k], j);
-                                if (lane >= j) r[j] = fma(-r[k], ljk, r[j]);
-                            }
-                        }
-                    }
-                }
+                for (int j = k + 1; j < CB; ++j) r[j] = fma(-lk, colb[j], r[j]);
+                __builtin_amdgcn_wave_barrier();
             }
             if (bad) {
                 if (lane == 0) {
@@ -151,28 +194,30 @@ __global__ __launch_bounds__(256) void chol2_kernel(int d, const double* __restr
         }
         __syncthreads();
         if (fail) return;   // uniform
-        // (b) panel rows below the block
+        // rows below the block exist only under a full block (nb == CB: a
+        // short block is the last one), so (b) and (c) run with compile-time
+        // trip counts
         const int m = d - kb - nb;
+        if (m <= 0) break;   // uniform: the last block
+        // (b) panel rows below the block
         for (int t = tid; t < m; t += nt) {
-            const int i = kb + nb + t;
+            const int i = kb + CB + t;
             double x[CB];
 #pragma unroll
-            for (int j = 0; j < CB; ++j) x[j] = j < nb ? S[i * LD + kb + j] : 0.0;
+            for (int j = 0; j < CB; ++j) x[j] = S[i * LD + kb + j];
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
-                if (j < nb) {
-                    double v = x[j];
+                double v = x[j];
 #pragma unroll
-                    for (int l = 0; l < j; ++l) v = fma(-x[l], S[(kb + j) * LD + kb + l], v);
-                    x[j] = v / S[(kb + j) * LD + kb + j];
-                }
+                for (int l = 0; l < j; ++l) v = fma(-x[l], S[(kb + j) * LD + kb + l], v);
+                x[j] = v * dinv[j];
             }
 #pragma unroll
-            for (int j = 0; j < CB; ++j)
-                if (j < nb) S[i * LD + kb + j] = x[j];
+            for (int j = 0; j < CB; ++j) S[i * LD + kb + j] = x[j];
         }
         __syncthreads();
-        // (c) trailing update on 4 x 4 tiles (ti >= tj)
+        // (c) trailing update on 4 x 4 tiles (ti >= tj); rows past d are read
+        // clamped and never stored
         const int mt = (m + 3) / 4;
         const int ntile = mt * (mt + 1) / 2;
         for (int tt = tid; tt < ntile; tt += nt) {
@@ -180,18 +225,26 @@ __global__ __launch_bounds__(256) void chol2_kernel(int d, const double* __restr
             while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
             while (ti * (ti + 1) / 2 > tt) --ti;
             const int tj = tt - ti * (ti + 1) / 2;
-            const int i0 = kb + nb + 4 * ti, j0 = kb + nb + 4 * tj;
+            const int i0 = kb + CB + 4 * ti, j0 = kb + CB + 4 * tj;
+            const double* rowi[4];
+            const double* rowj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                rowi[u] = S + min(i0 + u, d - 1) * LD + kb;
+                rowj[u] = S + min(j0 + u, d - 1) * LD + kb;
+            }
             double acc[4][4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-            for (int l = 0; l < nb; ++l) {
+#pragma unroll
+            for (int l = 0; l < CB; ++l) {
                 double pi[4], pj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    pi[u] = (i0 + u < d) ? S[(i0 + u) * LD + kb + l] : 0.0;
-                    pj[u] = (j0 + u < d) ? S[(j0 + u) * LD + kb + l] : 0.0;
+                    pi[u] = rowi[u][l];
+                    pj[u] = rowj[u][l];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
@@ -241,21 +294,6 @@ __global__ __launch_bounds__(256) void chol2_kernel(int d, const double* __restr
 // (so X^ = L2 T) and Z = col / sigma^(1/2) (so Y^ = L2^{-T} Z).
 // ---------------------------------------------------------------------------
 
-// 1/x and 1/sqrt(x) to full FP64 precision: the hardware estimates are good
-// to ~2^-24, two Newton steps bring them to rounding level.
-__device__ __forceinline__ double rcp2(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ double rsq2(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x * r;
-    r = fma(r, fma(-h, r, 0.5), r);
-    h = 0.5 * x * r;
-    return fma(r, fma(-h, r, 0.5), r);
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dmov(double v) {   // patterns where every lane reads a valid lane
     int2 p = __builtin_bit_cast(int2, v);
@@ -296,49 +334,69 @@ __device__ __forceinline__ double sumsq(const double (&x)[R]) {
     return qsum(s0 + s1);
 }
 
+// 1/x and 1/sqrt(x) after one Newton step (relative error ~1e-15): enough
+// where the value only steers the iteration
+__device__ __forceinline__ double rcp1(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq1(double x) {
+    const double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x * r;
+    return fma(r, fma(-h, r, 0.5), r);
+}
+
 // One rotation of the slot's pair.  The columns are kept scaled (Rutishauser's
-// fast form): the true columns are sa * a and sb * b, na and nb their squared
-// norms.  With the rotation  a' = c (a - t b),  b' = c (b + t a)  only the
-// scales take the factor c, and the stored vectors need two FMAs per row:
-//   a <- a - (t sb / sa) b,   b <- b + (t sa / sb) a_old,   sa, sb <- c sa, c sb.
+// fast form): the true columns are A = sa a and B = sb b, na and nb their
+// squared norms.  The rotation  A' = c (A - t B),  B' = c (B + t A)  is taken
+// as two in-place shears of the stored vectors and a change of the scales:
+//   b <- b + v a          with v = t sa / sb,      sb <- c sb,
+//   a <- a - u b (new b)  with u = t c^2 sb / sa,  sa <- sa sqrt(1 + t^2),
+// which gives exactly the rotated columns (substitute the new b into the
+// second shear: the coefficient of A is c (1 + t^2) (1 - t^2 c^2) = c).  Each
+// row costs two FMAs and no register copies.  The angle t is the root of
+// t^2 + 2 zeta t - 1 = 0 of smaller magnitude, zeta = (nb - na) / (2 gamma),
+// written as  t = sign(zeta) |2 gamma| / (|nb - na| + sqrt((nb - na)^2 + 4 gamma^2))
+// (no division by gamma); t itself needs no full precision, since the map is
+// an exact rotation for whatever t is used once c = 1 / sqrt(1 + t^2) is
+// exact for it, so only c takes two Newton steps.
 template <int R>
 __device__ __forceinline__ void jacobi_rotate(double (&a)[R], double (&b)[R], double& na, double& nb, double& sa,
                                               double& sb, double& offmax) {
-    double g0 = 0.0, g1 = 0.0;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
 #pragma unroll
-    for (int e = 0; e < R; e += 2) {
+    for (int e = 0; e < R; e += 4) {
         g0 = fma(a[e], b[e], g0);
         g1 = fma(a[e + 1], b[e + 1], g1);
+        g2 = fma(a[e + 2], b[e + 2], g2);
+        g3 = fma(a[e + 3], b[e + 3], g3);
     }
-    const double ga = qsum(g0 + g1) * (sa * sb);
+    const double ga = qsum((g0 + g1) + (g2 + g3)) * (sa * sb);
     const double al = na, be = nb;
-    const double rel = (ga != 0.0) ? fabs(ga) * rsq2(al * be) : 0.0;
+    const double rel = (ga != 0.0) ? fabs(ga) * rsq1(al * be) : 0.0;
     offmax = fmax(offmax, rel);
     const bool rot = rel > JACOBI_TOL;
     if (!__any(rot)) return;
-    // lanes whose pair needs no rotation apply the identity (u = v = 0, c = 1,
-    // exact), so that the update below runs unpredicated
-    double u = 0.0, v = 0.0, c = 1.0, tg = 0.0;
+    // lanes whose pair needs no rotation apply the identity (u = v = 0,
+    // scale factors 1, exact), so that the update below runs unpredicated
+    double u = 0.0, v = 0.0, fa = 1.0, c = 1.0, tg = 0.0;
     if (rot) {
-        // Rutishauser's rotation: zeta = (beta - alpha) / (2 gamma),
-        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2)
-        const double zeta = (be - al) * rcp2(2.0 * ga);
-        const double az = fabs(zeta);
-        const double w1 = fma(zeta, zeta, 1.0);
-        const double root = az < 1e150 ? w1 * rsq2(w1) : az;
-        const double t = copysign(rcp2(az + root), zeta);
-        c = rsq2(fma(t, t, 1.0));
-        u = t * sb * rcp2(sa);
+        const double diff = be - al, h = 2.0 * ga;
+        const double x = fma(diff, diff, h * h);
+        const double tm = fabs(h) * rcp1(fabs(diff) + x * rsq1(x));
+        const double t = ((diff >= 0.0) == (h >= 0.0)) ? tm : -tm;
+        const double w = fma(t, t, 1.0);
+        c = rsq2(w);
         v = t * sa * rcp2(sb);
+        u = t * (c * c) * sb * rcp2(sa);
+        fa = w * c;
         tg = t * ga;
     }
 #pragma unroll
-    for (int e = 0; e < R; ++e) {
-        const double x = a[e];
-        a[e] = fma(-u, b[e], x);
-        b[e] = fma(v, x, b[e]);
-    }
-    sa *= c;
+    for (int e = 0; e < R; ++e) b[e] = fma(v, a[e], b[e]);
+#pragma unroll
+    for (int e = 0; e < R; ++e) a[e] = fma(-u, b[e], a[e]);
+    sa *= fa;
     sb *= c;
     na = al - tg;
     nb = be + tg;
@@ -558,25 +616,56 @@ __global__ __launch_bounds__(D * 2) void jacobi_kernel(int d, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Y <- L^{-T} Y for the lower-triangular L (d x d, ld kMaxD) and d right-hand
-// sides (ld kMaxD): back substitution, one wavefront per right-hand side,
-// lane l holding rows l and l + 64.
+// Y <- L^{-T} Y for the lower-triangular L (d x d, ld kMaxD, zeros above the
+// diagonal) and d right-hand sides (ld kMaxD): back substitution in the
+// column (right-looking) form.  A workgroup of 16 wavefronts holds the rows
+// of L in LDS (row i contiguous, diagonal kept apart as reciprocals) and
+// solves 16 right-hand sides, one per wavefront, lane l holding rows l and
+// l + 64: at step i (descending) x_i = y_i / L(i,i) is broadcast from its
+// lane and every row k < i takes y_k -= L(i,k) x_i.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WAVE) void trsm_lt_kernel(int d, const double* __restrict__ L,
-                                                      double* __restrict__ Y) {
-    const int c = blockIdx.x, lane = threadIdx.x;
-    double* y = Y + (int64_t)c * kMaxD;
+constexpr int TRSM_W = 16;   // right-hand sides (wavefronts) per workgroup
+
+__global__ __launch_bounds__(TRSM_W * WAVE) void trsm_lt_kernel(int d, const double* __restrict__ L,
+                                                               double* __restrict__ Y) {
+    __shared__ double Lr[kMaxD * LD];   // Lr[i LD + k] = L(i, k), k < i; 0 elsewhere
+    __shared__ double rdiag[kMaxD];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    // column c of L (rows r = tid % 128, coalesced) into row r of Lr; 8 loads
+    // in flight per thread
+    constexpr int NT = TRSM_W * WAVE;
+    const int r = tid % kMaxD;
+    for (int c0 = tid / kMaxD; c0 < d; c0 += 8 * (NT / kMaxD)) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k * (NT / kMaxD);
+            v[k] = (c < d && r < d) ? L[(int64_t)c * kMaxD + r] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k * (NT / kMaxD);
+            if (c < d) {
+                Lr[r * LD + c] = (r == c) ? 0.0 : v[k];
+                if (r == c) rdiag[r] = 1.0 / v[k];
+            }
+        }
+    }
+    __syncthreads();
+    const int col = blockIdx.x * TRSM_W + w;
+    if (col >= d) return;   // no barrier follows
+    double* y = Y + (int64_t)col * kMaxD;
     const int j0 = lane, j1 = lane + 64;
     double y0 = j0 < d ? y[j0] : 0.0, y1 = j1 < d ? y[j1] : 0.0;
-    const double r0 = j0 < d ? 1.0 / L[(int64_t)j0 * kMaxD + j0] : 0.0;
-    const double r1 = j1 < d ? 1.0 / L[(int64_t)j1 * kMaxD + j1] : 0.0;
     for (int i = d - 1; i >= 0; --i) {
-        const double* li = L + (int64_t)i * kMaxD;   // column i of L = row i of L^T
-        const double l0 = (j0 > i && j0 < d) ? li[j0] : 0.0;
-        const double l1 = (j1 > i && j1 < d) ? li[j1] : 0.0;
-        const double s = wsum(fma(l0, y0, l1 * y1));
-        if (i == j0) y0 = (y0 - s) * r0;
-        if (i == j1) y1 = (y1 - s) * r1;
+        const double xi = readlane(i < 64 ? y0 : y1, i & 63) * rdiag[i];
+        if (lane == (i & 63)) {
+            if (i < 64) y0 = xi;
+            else y1 = xi;
+        }
+        const double* li = Lr + i * LD;
+        y0 = fma(-li[j0], xi, y0);   // L(i, k) = 0 for k >= i
+        if (i > 64) y1 = fma(-li[j1], xi, y1);
     }
     if (j0 < d) y[j0] = y0;
     if (j1 < d) y[j1] = y1;
@@ -947,7 +1036,8 @@ hipError_t small_lrep(hipStream_t st, int d, const double* Kh, const double* Mh,
     Seg l2{scratch + D2, kMaxD, d};
     e = gemm_nn(st, d, d, d, &l2, 1, T, kMaxD, Xh, kMaxD, 1.0, 0.0, work, work_elems);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(trsm_lt_kernel, dim3(d), dim3(WAVE), 0, st, d, scratch + D2, Yh);
+    hipLaunchKernelGGL(trsm_lt_kernel, dim3((d + TRSM_W - 1) / TRSM_W), dim3(TRSM_W * WAVE), 0, st, d,
+                       scratch + D2, Yh);
     return hipGetLastError();
 }
 
