@@ -68,6 +68,9 @@ WORKLOADS = {
     # one oracle iteration takes about a minute on the host: the baseline is a bounded sample
     "casida262144": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8,
                          cpu_iters=1),
+    # the same with the Step-6 CG passes reading an FP32 copy of L's rows (growth direction 1)
+    "casida262144f32": dict(kind="casida", n=262144, rank=256, seed=1003, nev=128, block=64, window=32, tol=1e-8,
+                            cpu_iters=1, precision=4),
     # generalized LREP K x = lambda B y, M y = lambda B x with a diagonal metric B (growth direction f4)
     "dense8192metric": dict(kind="dense", n=8192, seed=1002, nev=64, block=64, window=32, tol=1e-10, zeros=0,
                             metric_seed=1105),
@@ -368,8 +371,9 @@ def describe(w):
             z += "; generalized LREP K x = lambda B y, M y = lambda B x, B = diag(b), b log-uniform on [0.25, 4]"
         return (f"dense FP64 n={w['n']}: K=Q1 diag(k) Q1^T, M=Q2 diag(m) Q2^T, Haar Q1/Q2, k,m~U[0.5,10]{z}; "
                 f"nev={w['nev']}, block={w['block']}, window={w['window']}, tol={w['tol']:g}")
+    z = "; Step-6 CG passes read an FP32 copy of L's rows (FP64 products)" if w.get("precision", 0) == 4 else ""
     return (f"Casida low-rank FP64 n={w['n']}: K=diag(delta), M=diag(delta)+2LL^T, delta~U[0.1,20] sorted, "
-            f"L n x {w['rank']} Gaussian/sqrt(n); nev={w['nev']}, block={w['block']}, window={w['window']}, "
+            f"L n x {w['rank']} Gaussian/sqrt(n){z}; nev={w['nev']}, block={w['block']}, window={w['window']}, "
             f"tol={w['tol']:g}")
 
 
@@ -571,6 +575,10 @@ def main():
         elif w["kind"] == "dense":
             kname = "apply_stream_kernel (CG block apply, w=%d)" % window
             abytes = 8.0 * n * n + 16.0 * n * window
+        elif w.get("precision", 0) == 4:
+            kname = ("fcg_pass_M_kernel<float> (fused CG step on M = diag(delta) + 2 L L^T, w=%d: FP32 rows of L "
+                     "read once, x, r, p read and written, delta read)" % window)
+            abytes = 4.0 * n * w["rank"] + 48.0 * n * window + 8.0 * n
         else:
             kname = ("fcg_pass_M_kernel (fused CG step on M = diag(delta) + 2 L L^T, w=%d: L read once, "
                      "x, r, p read and written, delta read)" % window)
@@ -640,7 +648,8 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": {0: "f64", 1: "bf16 CG applies (f32 accumulate), f64 elsewhere",
                   2: "f16 CG applies (f32 accumulate), f64 elsewhere",
-                  3: "bf16x3 CG applies (f32 accumulate), f64 elsewhere"}[w.get("precision", 0)],
+                  3: "bf16x3 CG applies (f32 accumulate), f64 elsewhere",
+                  4: "f64 (CG passes read an f32 copy of L)"}[w.get("precision", 0)],
         "data": "synthetic",
         "config": {"workload": describe(w), "n": n, "nev": nev, "block": block, "window": window, "tol": tol,
                    "seed": w["seed"], "parallelism": "single GPU"},

@@ -97,7 +97,17 @@ typedef struct lrep_solve_opts {
                                  The 16-bit copies (2 n^2 bytes each, 6 n^2 for
                                  BF16x3, charged to the context budget) are made at
                                  the first such solve and kept with the operator; n
-                                 must be a multiple of 8.                             */
+                                 must be a multiple of 8.  Low-rank operators ignore
+                                 1-3.  4 (low-rank operators with rank >= 1 only,
+                                 else LREP_EINVAL): the fused CG steps of Step 6 read
+                                 an FP32 copy of L's rows (each value rounded to
+                                 nearest even once, widened exactly to FP64 in the
+                                 kernel; FP64 products and sums), half the bytes of L
+                                 per step; the CG solves the system of diag(delta) +
+                                 2 L~ L~^T with L~ the rounded L, a relative change of
+                                 ~1e-7, far below the CG's 1e-2 tolerance.  The copy
+                                 (4 n ceil64(rank) bytes, charged to the budget) is
+                                 made at the first such solve.                        */
     int32_t profile;          /* 1: time every Step-6 operator apply with HIP events on
                                  the solve's stream (results in lrep_stats_t.prof_*)  */
     double  rebiorth_tol;  /* re-biorthogonalise U,V when max|U^T V - I| exceeds this

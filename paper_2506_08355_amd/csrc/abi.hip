@@ -462,6 +462,9 @@ int lrep_set_metric(lrep_op_t op, int64_t n_b, const double* b, uint32_t flags) 
         e = metric_scale_diag(c->stream, n, op->delta, sv);
         if (e == hipSuccess && op->rank > 0) e = metric_scale_rows(c->stream, n, (int)op->rank, op->L, op->ldl, sv, false);
         if (e == hipSuccess && op->Lr) e = lowrank_make_rows(c->stream, (int)n, (int)op->rank, op->L, op->ldl, op->Lr);
+        // an FP32 copy, if any, was made from the unscaled rows
+        std::lock_guard<std::mutex> lk(op->mu16);
+        op->Lr32buf.release();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {

@@ -92,6 +92,10 @@ struct Op {
     std::mutex mu16;
     int prec16 = 0;
     DevBuf K16buf, M16buf;
+    // FP32 copy of the rows of L for the fused CG passes (precision 4), made on
+    // first use (under mu16); dropped when the operator data changes
+    DevBuf Lr32buf;
+    const float* Lr32() const { return reinterpret_cast<const float*>(Lr32buf.p); }
     const uint16_t* K16() const { return reinterpret_cast<const uint16_t*>(K16buf.p); }
     const uint16_t* M16() const { return reinterpret_cast<const uint16_t*>(M16buf.p); }
     bool null_on_M() const { return (flags & LREP_NULL_ON_M) != 0; }

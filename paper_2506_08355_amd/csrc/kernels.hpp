@@ -93,6 +93,9 @@ hipError_t cg_dense_apply(hipStream_t st, int n, int w, const double* A, int64_t
 int64_t lowrank_row_ld(int64_t r);
 // Lr (n x lowrank_row_ld(r), row-major, zero-padded) = L (n x r, ld ldl), r <= 256
 hipError_t lowrank_make_rows(hipStream_t st, int n, int r, const double* L, int64_t ldl, double* Lr);
+// Lr32 = the FP32 copy of the row-major Lr (n x lowrank_row_ld(r)), each value
+// rounded to nearest even
+hipError_t lowrank_rows_f32(hipStream_t st, int n, int r, const double* Lr, float* Lr32);
 // C = delta o Y + 2 L (L^T Y) from the row-major copy, w <= 32 columns of Y
 // (ld even, 16-byte aligned); `work` holds 256 * 32 + nchunk * 8192 doubles.
 // With pq, also pq[t * 32 + j] = the sum over the 64-row tile t of Y[:, j] C[:, j].
@@ -187,14 +190,17 @@ hipError_t cg_direction(hipStream_t st, int n, int w, const CgState& s);
 // own recurrence (L^T p_new = L^T r_new + beta L^T p), x += alpha p,
 // r -= alpha A p, and the sums that give the next alpha and beta (L is read
 // once per step), then a fixed-order reduction and finishing launch.
-// `work` holds fused_cg_work_elems(n, r, w) doubles.
+// `work` holds fused_cg_work_elems(n, r, w) doubles.  With Lr32 (the FP32 copy
+// of Lr) the steps read L from it, widened exactly to FP64 (half the bytes of
+// L; the products are those of the FP32-rounded L); the first T = L^T b still
+// comes from Lr.
 size_t fused_cg_work_elems(int n, int r, int w);
 hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                          const CgState& s, const double* B, int64_t ldb, double tol, double* work,
                          size_t work_elems);
 hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                          const CgState& s, double tol, double* work, size_t work_elems, hipEvent_t* ev = nullptr,
-                         int* flag_log = nullptr);
+                         int* flag_log = nullptr, const float* Lr32 = nullptr);
 // Bx = I - (G - I)^T / 2, By = I - (G - I) / 2 for G = X^T Y (c x c): the
 // first-order correction (X Bx)^T (Y By) = I + O(|G - I|^2)
 hipError_t biorth_fix_coef(hipStream_t st, int c, const double* G, int64_t ldg, double* Bx, double* By, int64_t ldb);

@@ -326,8 +326,17 @@ constexpr int PSR = PT * FMS;        // doubles of a pipeline's r
 constexpr int FREC = 128;            // column sums per record: (rho, a, b, 0) for 32 columns
 constexpr int FSINK = 6;             // doubles of the store sink per thread
 
+// two consecutive entries of a row of L as loaded: a 16-byte load of the FP64
+// rows or an 8-byte load of the FP32 rows; FP32 values are widened exactly to
+// FP64 where they are used (LDS store, MFMA operand), so that registers hold
+// the narrow form while the loads are in flight
+template <typename LT> struct LPair;
+template <> struct LPair<double> { using type = double2; };
+template <> struct LPair<float> { using type = float2; };
+
+template <typename LT>
 __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, int tpw,
-                                                         const double* __restrict__ Lr,
+                                                         const LT* __restrict__ Lr,
                                                          const double* __restrict__ delta, double* __restrict__ X,
                                                          double* __restrict__ R, double* __restrict__ P,
                                                          const double* __restrict__ T,
@@ -337,6 +346,7 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
                                                          double* __restrict__ rec, int stride,
                                                          double* __restrict__ sink,
                                                          int* __restrict__ flag_log) {
+    using P2 = typename LPair<LT>::type;
     const int on = *any;
     if (flag_log && blockIdx.x == 0 && threadIdx.x == 0) *flag_log = on;
     if (on == 0) return;
@@ -355,7 +365,7 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
     // multiply it by the zero rows of T: every wavefront runs the same
     // branch-free code, so the compiler can count the loads in flight exactly
     const bool hasL = 64 * v < ldr;
-    const double* lbase = Lr + (hasL ? 64 * v : 0) + 2 * c;
+    const LT* lbase = Lr + (hasL ? 64 * v : 0) + 2 * c;
     double* slp = sl + pp * PSL;          // the pipeline's four slices / partials
     double* slv = slp + v * PT * FLS;     // this wavefront's
     double* srp = sr + pp * PSR;
@@ -380,14 +390,14 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
     // A tile's slice; rows beyond n read row n - 1 and tiles beyond the
     // pipeline's last read its last tile (an L2 hit); those rows are masked
     // in phase B.  No select on loaded values: nothing waits for them early.
-    auto loadL = [&](double2 (&a)[4][2], int j) {
+    auto loadL = [&](P2 (&a)[4][2], int j) {
         const int tl = tile_of(j);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int row = min(tl * PT + 4 * s + g, n - 1);
-            const double* lp = lbase + (int64_t)row * ldr;
+            const LT* lp = lbase + (int64_t)row * ldr;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) a[s][h] = *reinterpret_cast<const double2*>(lp + 32 * h);
+            for (int h = 0; h < 2; ++h) a[s][h] = *reinterpret_cast<const P2*>(lp + 32 * h);
         }
     };
     // A tile's x, r, p, delta at rows (2 eq, 2 eq + 1): one 16-byte load per
@@ -403,8 +413,10 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
     // S += L_slice^T r (rows 4 s + g): block u of S takes k = 64 v + 32 (u / 2)
     // + 2 c + u % 2 in its row c, so that item i of its 16 x 16 result is
     // S row ku(u, i) = 64 v + 32 (u / 2) + 8 i + 2 g + u % 2
-    auto lpart = [](const double2 (&a)[4][2], int s, int u) { return (u & 1) ? a[s][u >> 1].y : a[s][u >> 1].x; };
-    auto stage4 = [&](const double2 (&a)[4][2]) {
+    auto lpart = [](const P2 (&a)[4][2], int s, int u) {
+        return (double)((u & 1) ? a[s][u >> 1].y : a[s][u >> 1].x);
+    };
+    auto stage4 = [&](const P2 (&a)[4][2]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const double b0 = srp[(4 * s + g) * FMS + c], b1 = srp[(4 * s + g) * FMS + 16 + c];
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
 
     double2 vv[4];
     // one tile: cur holds its slice, old the previous tile's (zero before the first)
-    auto tile_step = [&](double2 (&cur)[4][2], double2 (&old)[4][2], int j) {
+    auto tile_step = [&](P2 (&cur)[4][2], P2 (&old)[4][2], int j) {
         // ---- phase A: the slice to LDS; then the partial product L_slice
         // T_slice (row c, k = 4 ks + g) interleaved with the previous tile's
         // S += L^T r (slice in registers), so that the LDS reads of the one
@@ -429,8 +441,8 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                slv[(4 * s + g) * FLS + 32 * h + 2 * c] = cur[s][h].x;
-                slv[(4 * s + g) * FLS + 32 * h + 2 * c + 1] = cur[s][h].y;
+                slv[(4 * s + g) * FLS + 32 * h + 2 * c] = (double)cur[s][h].x;
+                slv[(4 * s + g) * FLS + 32 * h + 2 * c + 1] = (double)cur[s][h].y;
             }
         double rb0[4], rb1[4];
 #pragma unroll
@@ -511,9 +523,9 @@ __global__ __launch_bounds__(512) void fcg_pass_M_kernel(int n, int ldr, int w, 
         __syncthreads();
     };
 
-    double2 la[4][2], lb[4][2];
+    P2 la[4][2], lb[4][2];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) lb[s][0] = lb[s][1] = double2{0.0, 0.0};
+    for (int s = 0; s < 4; ++s) lb[s][0] = lb[s][1] = P2{0, 0};
     loadL(la, 0);
     loadV(vv, 0);
     __syncthreads();
@@ -779,9 +791,25 @@ __global__ __launch_bounds__(32 * FIN_PH) void fcg_finish_kernel(int w, int ldr,
     }
 }
 
+// the FP32 copy of the rows of L (each value rounded to nearest even once),
+// padding columns included
+__global__ __launch_bounds__(256) void rows_f32_kernel(int64_t count, const double* __restrict__ Lr,
+                                                       float* __restrict__ Lr32) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        Lr32[i] = (float)Lr[i];
+}
+
 }  // namespace
 
 int64_t lowrank_row_ld(int64_t r) { return ((r + 63) / 64) * 64; }
+
+hipError_t lowrank_rows_f32(hipStream_t st, int n, int r, const double* Lr, float* Lr32) {
+    if (n < 1 || r < 1 || r > 256 || !Lr || !Lr32) return hipErrorInvalidValue;
+    const int64_t count = (int64_t)n * lowrank_row_ld(r);
+    hipLaunchKernelGGL(rows_f32_kernel, dim3((unsigned)std::min<int64_t>(4096, (count + 255) / 256)), dim3(256), 0,
+                       st, count, Lr, Lr32);
+    return hipGetLastError();
+}
 
 hipError_t lowrank_make_rows(hipStream_t st, int n, int r, const double* L, int64_t ldl, double* Lr) {
     const int ldr = (int)lowrank_row_ld(r);
@@ -880,9 +908,10 @@ hipError_t fused_cg_init(hipStream_t st, int n, int r, int w, const double* delt
 
 hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delta, const double* Lr,
                          const CgState& s, double tol, double* work, size_t work_elems, hipEvent_t* ev,
-                         int* flag_log) {
+                         int* flag_log, const float* Lr32) {
     if (n < 64 || (n & 1) || w < 1 || w > 32 || (Lr && (r < 1 || r > 256)) ||
-        work_elems < fused_cg_work_elems(n, Lr ? r : 0, w) || (reinterpret_cast<uintptr_t>(Lr) & 15))
+        work_elems < fused_cg_work_elems(n, Lr ? r : 0, w) || (reinterpret_cast<uintptr_t>(Lr) & 15) ||
+        (reinterpret_cast<uintptr_t>(Lr32) & 7))
         return hipErrorInvalidValue;
     if (Lr) {
         const int ldr = (int)lowrank_row_ld(r);
@@ -895,8 +924,14 @@ hipError_t fused_cg_step(hipStream_t st, int n, int r, int w, const double* delt
         double* red = work + (size_t)ngrid * stride;
         double* sink = red + stride;
         if (ev) (void)hipEventRecord(ev[0], st);
-        hipLaunchKernelGGL(fcg_pass_M_kernel, dim3(ngrid), dim3(512), 0, st, n, ldr, w, tpw, Lr, delta, s.X, s.R, s.P,
-                           s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, sink, flag_log);
+        if (Lr32)
+            hipLaunchKernelGGL(fcg_pass_M_kernel<float>, dim3(ngrid), dim3(512), 0, st, n, ldr, w, tpw, Lr32, delta,
+                               s.X, s.R, s.P, s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, sink,
+                               flag_log);
+        else
+            hipLaunchKernelGGL(fcg_pass_M_kernel<double>, dim3(ngrid), dim3(512), 0, st, n, ldr, w, tpw, Lr, delta,
+                               s.X, s.R, s.P, s.T, s.alpha, s.beta, s.active, s.any_active, rec, stride, sink,
+                               flag_log);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(fcg_reduce_kernel, dim3((stride + 31) / 32), dim3(32 * FIN_PH), 0, st, ngrid, stride, rec,
                            red, s.any_active, 0);

@@ -190,9 +190,9 @@ struct Solver {
         } else if (op->kind == 2) {   // caller-supplied products: no byte model
             prof_b.push_back(0.0);
             prof_f.push_back(0.0);
-        } else if (fused) {   // fused low-rank M step: L once; x, r, p read and written; delta
+        } else if (fused) {   // fused low-rank M step: L once (FP64 or FP32 rows); x, r, p read and written; delta
             const double r = (double)op->rank;
-            prof_b.push_back(8.0 * nn * r + 48.0 * nn * c + 8.0 * nn);
+            prof_b.push_back((o.precision == 4 ? 4.0 : 8.0) * nn * r + 48.0 * nn * c + 8.0 * nn);
             prof_f.push_back(4.0 * nn * r * c + 14.0 * nn * c);
         } else {   // low-rank M: L read twice, Y read twice, result written once
             const double r = (double)op->rank;
@@ -428,7 +428,8 @@ struct Solver {
             }
             int* logslot = nullptr;
             hipEvent_t* ev = (o.profile && kind == 2) ? prof_next(nw, &logslot, 0, true) : nullptr;
-            CK(fused_cg_step(st, (int)n, r, nw, op->delta, Lr, s, cgtol, gwork.p, GEMM_WORK_ELEMS, ev, logslot));
+            CK(fused_cg_step(st, (int)n, r, nw, op->delta, Lr, s, cgtol, gwork.p, GEMM_WORK_ELEMS, ev, logslot,
+                             kind == 2 && o.precision == 4 ? op->Lr32() : nullptr));
         }
         return LREP_OK;
     }
@@ -1150,7 +1151,7 @@ int solve_options(const lrep_solve_opts_t* opts, int64_t block, lrep_solve_opts_
     if (!(o.cg_tol > 0)) o.cg_tol = 1e-2;
     if (!(o.rebiorth_tol > 0)) o.rebiorth_tol = 1e-12;
     if (o.refresh <= 0) o.refresh = 8;
-    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 3 || o.fused_cg < -1 || o.fused_cg > 1 ||
+    if (o.graphs < -1 || o.graphs > 1 || o.precision < 0 || o.precision > 4 || o.fused_cg < -1 || o.fused_cg > 1 ||
         o.serve_batch < -1 || o.serve_batch > 0)
         return LREP_EINVAL;
     return LREP_OK;
@@ -1166,7 +1167,9 @@ int solve_configure(Solver& s, Op* op, hipStream_t st, int64_t nev, int64_t bloc
     // with other requests' (not under graph capture or per-launch profiling)
     s.batch = served && o.serve_batch == 0 && (op->kind == 0 || op->kind == 1) && o.graphs != 1 && !o.profile &&
               o.window <= 32;
-    if (o.precision != 0 && op->kind == 0 && (op->n % 8 != 0 || op->n < 64)) return LREP_EINVAL;
+    if (o.precision >= 1 && o.precision <= 3 && op->kind == 0 && (op->n % 8 != 0 || op->n < 64)) return LREP_EINVAL;
+    // FP32 rows of L for the fused CG passes: low-rank operators with L only
+    if (o.precision == 4 && (op->kind != 1 || !op->Lr)) return LREP_EINVAL;
     if (o.init_U && o.ld_init < op->n) return LREP_EINVAL;
     s.o = o;
     s.b = (int)block;
@@ -1194,6 +1197,10 @@ int solve_footprint(Op* op, int64_t nev, int64_t block, double tol, const lrep_s
         std::lock_guard<std::mutex> g(op->mu16);
         if (op->prec16 != o.precision)
             total += 2 * (size_t)(o.precision == 3 ? 3 : 1) * op->n * op->n * sizeof(uint16_t);
+    }
+    if (o.precision == 4) {
+        std::lock_guard<std::mutex> g(op->mu16);
+        if (!op->Lr32buf.p) total += (size_t)op->n * lowrank_row_ld(op->rank) * sizeof(float);
     }
     *bytes = total;
     return LREP_OK;
@@ -1228,6 +1235,22 @@ int solve(Op* op, hipStream_t st, int64_t nev, int64_t block, double tol, const 
                 return LREP_EDEVICE;
             }
             op->prec16 = o.precision;
+        }
+    }
+    if (o.precision == 4) {
+        // FP32 rows of L for the fused CG passes
+        std::lock_guard<std::mutex> g(op->mu16);
+        if (!op->Lr32buf.p) {
+            const int64_t ldr = lowrank_row_ld(op->rank);
+            int rc = op->Lr32buf.alloc(op->ctx, (size_t)op->n * ldr * sizeof(float));
+            if (rc != LREP_OK) return rc;
+            hipError_t e = lowrank_rows_f32(st, (int)op->n, (int)op->rank, op->Lr, const_cast<float*>(op->Lr32()));
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                op->Lr32buf.release();
+                op->ctx->set_error(hipGetErrorString(e));
+                return LREP_EDEVICE;
+            }
         }
     }
     int rc = s.alloc();

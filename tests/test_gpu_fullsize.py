@@ -83,15 +83,18 @@ def test_config2_full_size(ctx, zeros, seed, precision):
         assert np.abs(null.T @ X).max() <= 1e-10
 
 
-def test_config3_casida_full_size(ctx):
+@pytest.mark.parametrize("precision", [0, 4], ids=["fp64", "fp32_rows_cg"])
+def test_config3_casida_full_size(ctx, precision):
+    """The Casida workload at full size; precision 4 runs the Step-6 CG
+    passes on the FP32 copy of L's rows and must meet the same bars."""
     n, r, nev, block, window, tol = 262144, 256, 128, 64, 32, 1e-8
-    print(f"[fullsize] casida n={n} rank={r}", flush=True)
+    print(f"[fullsize] casida n={n} rank={r} precision={precision}", flush=True)
     f = gen.casida_factors(n, r, 1003)
     delta_d = torch.from_numpy(f.delta).to("cuda:0")
     L_d = torch.from_numpy(np.ascontiguousarray(f.L.T)).to("cuda:0").T
     U, _ = gen.init_block(n, block + 2 * window, 7)
     op = L.lrep_create_lowrank(ctx, delta_d, L_d)
-    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U)
+    rc, st, lam, X, Y = solve(ctx, op, n, nev, block, window, tol, U, precision=precision)
     L.lrep_destroy_op(op)
     assert rc == L.LREP_OK, L.lrep_last_error(ctx)
     Lh, dl = f.L, f.delta

@@ -187,6 +187,40 @@ def test_casida_fused_cg(ctx, n, r, fused):
     assert st.applies_M > 0 and st.applies_K > 0
 
 
+@pytest.mark.parametrize("n,r", [(1502, 100), (3002, 256), (2048, 64)])
+def test_casida_fused_cg_fp32_rows(ctx, n, r):
+    """precision 4: the fused CG passes read an FP32 copy of L's rows (only
+    the Step-6 CG changes, by ~1e-7 relative against its 1e-2 tolerance); the
+    returned pairs meet the same oracle bars as the FP64 solve.  Ragged row
+    tiles (1502, 3002) and 1, 2 or 4 wavefronts of columns (64, 100, 256)."""
+    nev, block, window, tol = 16, 16, 8, 1e-9
+    print(f"[fused cg fp32 rows] n={n} rank={r}", flush=True)
+    f = gen.casida_factors(n, r, 1000 + r)
+    U, _ = gen.init_block(n, block + 2 * window, 7)
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    rc, st, lam, X, Y = gpu_solve(ctx, op, n, nev, block, tol, window=window, init=U, precision=4)
+    L.lrep_destroy_op(op)
+    assert rc == L.LREP_OK, L.lrep_last_error(ctx)
+    cop = oracle.CasidaOperator(f.delta, f.L)
+    ref = oracle.bosp_solve(cop, nev, block, tol, window=window, init=(U, U))
+    normH = np.linalg.norm(f.M(), 2)
+    check_pair(lam, X, Y, ref.lam, cop.apply_K, cop.apply_M, normH)
+    assert exact.casida_count_below(f.delta, f.L, lam[-1] * (1 + 1e-9)) == nev
+
+
+def test_fp32_rows_only_for_low_rank(ctx):
+    """precision 4 on a dense operator is rejected before any work, and
+    precision 5 on any operator."""
+    n = 256
+    K, M, _ = gen.dense_operator(n, 3)
+    op = L.lrep_create_dense(ctx, dev_colmajor(K, torch), dev_colmajor(M, torch))
+    rc, *_ = gpu_solve(ctx, op, n, 4, 8, 1e-8, precision=4)
+    assert rc == L.LREP_EINVAL
+    rc, *_ = gpu_solve(ctx, op, n, 4, 8, 1e-8, precision=5)
+    assert rc == L.LREP_EINVAL
+    L.lrep_destroy_op(op)
+
+
 def test_error_paths(ctx):
     n = 64
     K, M, f = gen.dense_operator(n, 3)
