@@ -84,6 +84,7 @@ WORKLOADS = {
 TRAFFIC = {
     "dense8192": ("apply_stream_kernel.dense8192.traffic.md", "apply.hip", "apply_hip_sha256"),
     "casida262144": ("lowrank_cg.casida262144.traffic.md", "lowrank.hip", "lowrank_hip_sha256"),
+    "casida262144f32": ("lowrank_cg_f32rows.casida262144.traffic.md", "lowrank.hip", "lowrank_hip_sha256"),
 }
 CSRC = os.path.join(ROOT, "paper_2506_08355_amd", "csrc")
 
