@@ -84,6 +84,29 @@ def test_small_lrep_against_oracle(ctx, d, cond):
     assert np.abs(Mh @ Y - X * lam_h).max() <= 1e-11 * scale * max(np.abs(Y).max(), 1)
 
 
+@pytest.mark.parametrize("d", [37, 100, 128])
+def test_small_lrep_uses_the_symmetric_part(ctx, d):
+    """The projected matrices are symmetric only up to rounding (K^ = U^T (K U)
+    with carried images); the small solver factors their symmetric parts
+    (K^ + K^T)/2.  A non-symmetric perturbation of relative size 1e-3 makes
+    a factorisation of one triangle alone (or of one element twice) move the
+    eigenvalues by ~8e-4, far above the 1e-10 tolerance."""
+    rng = np.random.default_rng(500 + d)
+    Kh = _spd(rng, d, 1e2) + 1e-3 * rng.standard_normal((d, d))
+    Mh = _spd(rng, d, 1e2) + 1e-3 * rng.standard_normal((d, d))
+    lam = torch.zeros(d, dtype=torch.float64, device="cuda:0")
+    Xh, Yh = dev_empty(128, 128, torch), dev_empty(128, 128, torch)
+    rc = L.lrep_test_small_lrep(ctx, dev_colmajor(Kh, torch), dev_colmajor(Mh, torch), lam, Xh, Yh)
+    assert rc == L.LREP_OK
+    lam_h, X, Y = host(lam), host(Xh)[:d, :d], host(Yh)[:d, :d]
+    ref, _, _ = oracle.small_lrep(Kh, Mh, d)
+    np.testing.assert_allclose(lam_h, ref, rtol=1e-10)
+    Ks, Ms = 0.5 * (Kh + Kh.T), 0.5 * (Mh + Mh.T)
+    scale = np.abs(Ks).max() + np.abs(Ms).max()
+    assert np.abs(Ks @ X - Y * lam_h).max() <= 1e-11 * scale * max(np.abs(X).max(), 1)
+    assert np.abs(Ms @ Y - X * lam_h).max() <= 1e-11 * scale * max(np.abs(Y).max(), 1)
+
+
 def test_small_lrep_reports_not_spd(ctx):
     d = 6
     Kh = np.diag([1.0, 2.0, -1.0, 3.0, 1.0, 1.0])
