@@ -265,3 +265,42 @@ def test_concurrent_cg_solves_run_batched_and_bitwise_alone(served):
                 assert batched > 0 and shared_cols > 0, (o, batched, shared_cols)
             else:
                 assert batched == 0 and shared_cols == 0, (o, batched, shared_cols)
+
+
+def test_concurrent_fp32_row_requests_share_one_copy(served):
+    """precision 4 (the CG passes on the FP32 rows of L) under serving: six
+    requests submitted at once on a fresh low-rank operator race to make its
+    FP32 copy (made once, under the operator's lock) and batch their CG
+    solves; every result is bitwise the same request solved alone afterwards,
+    and its eigenvalues match the FP64 solve to 1e-10."""
+    ctx = served[0]
+    n, r, nev, block, window = 16384, 64, 8, 16, 8
+    f = gen.casida_factors(n, r, 1205)
+    op = L.lrep_create_lowrank(ctx, dev_colmajor(f.delta, torch), dev_colmajor(f.L, torch))
+    U = np.asfortranarray(gen.init_block(n, block + 2 * window, 310)[0])
+    jobs = []
+    for c in range(6):
+        lam, X, Y = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+        opts = L.make_opts(window=window, init=U, precision=4)
+        jobs.append((L.lrep_submit(ctx, op, nev, block, 1e-8, opts, lam, X, Y), lam, X, Y, opts))
+    done, deadline = set(), time.time() + 120
+    while len(done) < len(jobs) and time.time() < deadline:
+        for t, *_ in jobs:
+            if t not in done:
+                rc, _ = L.lrep_poll(ctx, t)
+                if rc != L.LREP_EAGAIN:
+                    assert rc == L.LREP_OK, rc
+                    done.add(t)
+        time.sleep(0.002)
+    assert len(done) == len(jobs), "served requests did not finish"
+    lam1, X1, Y1 = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+    rc, _ = L.lrep_solve(op, n, nev, block, 1e-8, L.make_opts(window=window, init=U, precision=4), lam1, X1, Y1,
+                         ctx=ctx)
+    assert rc == L.LREP_OK
+    lam0, X0, Y0 = np.zeros(nev), np.zeros((n, nev), order="F"), np.zeros((n, nev), order="F")
+    rc, _ = L.lrep_solve(op, n, nev, block, 1e-8, L.make_opts(window=window, init=U), lam0, X0, Y0, ctx=ctx)
+    assert rc == L.LREP_OK
+    L.lrep_destroy_op(op)
+    for t, lam, X, Y, _ in jobs:
+        assert np.array_equal(lam, lam1) and np.array_equal(X, X1) and np.array_equal(Y, Y1)
+    np.testing.assert_allclose(lam1, lam0, rtol=1e-10, atol=0)
